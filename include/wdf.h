@@ -1,0 +1,205 @@
+/*
+ * wdf.h: C ABI of the MI355X (gfx950) Background-SHAP library.
+ *
+ * The library computes, for every consumer row c and feature i, the
+ * Background (interventional) Shapley value
+ *     phi_i(c) = Shapley value of v(S) = (1/|B|) sum_b f(c_S, b_rest)
+ * of a decision-tree ensemble f, by the WOODELF decomposition of arXiv
+ * 2511.09376 (Section 7, Formula eq:bg_shap_derivation; Alg. 3):
+ *   1. decision patterns of every background row at every leaf
+ *      (Def. Decision Pattern, Alg. 1),
+ *   2. their per-leaf histogram vc[l][p_b] (Section 7 step (d)),
+ *   3. s_{l,i} = w_l * M_{l,i} * f_l with the pattern-to-coefficient matrix
+ *      M built from the four rules (Section 5, Alg. 2) and the linear-time
+ *      formula (Formula shap_simplified_formula), as a dense matrix product,
+ *   4. phi_i(c) = sum_l s_{l,i}[P[l][c]] (Section 7 step (g)).
+ * Sibling leaves share one table indexed by the left leaf's pattern
+ * (Section 9.1, improvement 3).  The same machinery gives Banzhaf values
+ * (Formula banzhaf_simplified_formula) and Path-Dependent SHAP (Section 8).
+ *
+ * Conventions
+ *   - A row goes left at an inner node iff x[feature] < threshold (float32
+ *     compare, Def. Decision Tree); a NaN feature value goes to the side
+ *     named by the node's default_left byte.
+ *   - Matrices are column-major float32: element (feature f, row r) of X is
+ *     X[f * ldx + r].  phi uses the same layout with ldphi.
+ *   - Every function returns WDF_OK (0) or a negative error code; the text of
+ *     the last error on the calling thread is returned by wdf_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Handles are owned by the library and freed by the matching destroy call.
+ *     A context is bound to one HIP device.  Calls taking a `hip_stream`
+ *     enqueue on it; NULL means the HIP null (legacy default) stream.
+ */
+#ifndef WDF_H
+#define WDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WDF_OK = 0,
+  WDF_E_INVALID_ARG = -1,   /* null pointer, bad size, malformed ensemble */
+  WDF_E_UNSUPPORTED = -2,   /* a path deeper than WDF_MAX_DEPTH, too many features */
+  WDF_E_OOM = -3,           /* device or host allocation failed */
+  WDF_E_DEVICE = -4,        /* a HIP call failed; the HIP error text is in wdf_last_error() */
+  WDF_E_BUSY = -5,          /* serving queue full */
+  WDF_E_TIMEOUT = -6,       /* wait timed out */
+  WDF_E_COMPILE = -7        /* runtime specialisation of a kernel failed */
+};
+
+#define WDF_MAX_DEPTH 8       /* inner nodes on any root-to-leaf path */
+#define WDF_MAX_FEATURES 4096
+
+/* Values computed from the cube of a (consumer, background) pattern pair. */
+enum {
+  WDF_SHAPLEY = 0,          /* Formula shap_simplified_formula */
+  WDF_BANZHAF = 1           /* Formula banzhaf_simplified_formula */
+};
+
+/* Kernel choice for the pattern, histogram and gather steps. */
+enum {
+  WDF_KERNEL_AUTO = 0,      /* model-specialised kernels when they compile, else generic */
+  WDF_KERNEL_GENERIC = 1,   /* data-driven kernels that walk each leaf path */
+  WDF_KERNEL_SPECIALISED = 2/* kernels compiled for this ensemble at load time (hipRTC) */
+};
+
+typedef struct wdf_ctx wdf_ctx;
+typedef struct wdf_model wdf_model;
+typedef struct wdf_bg wdf_bg;
+
+/* Last error message of the calling thread ("" when none).  The pointer stays
+ * valid until the next wdf call on the same thread. */
+const char *wdf_last_error(void);
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int wdf_create(int device, wdf_ctx **out);
+void wdf_destroy(wdf_ctx *ctx);
+
+/* Ensemble description: host arrays, trees concatenated; node indices in
+ * left/right are local to the tree (0 = the tree's first node = its root).
+ * Leaves have feature = -1 and left = right = -1.  (Def. Decision Tree.) */
+typedef struct {
+  int32_t n_trees;
+  int32_t n_features;
+  const int64_t *node_offset;   /* n_trees + 1 entries, node_offset[0] = 0 */
+  const int32_t *feature;       /* split feature, -1 for leaves */
+  const int32_t *left;          /* local index of the left child, -1 for leaves */
+  const int32_t *right;         /* local index of the right child, -1 for leaves */
+  const float *threshold;       /* x < threshold goes left */
+  const float *value;           /* leaf value w_l (ignored for inner nodes) */
+  const uint8_t *default_left;  /* NaN direction: nonzero = left */
+  const double *cover;          /* training rows reaching each node (Section 8); may be NULL */
+} wdf_model_desc;
+
+/* Validate and copy an ensemble (the caller may free its arrays on return),
+ * extract its root-to-leaf paths, pair sibling leaves, build the
+ * pattern-to-coefficient matrices in double precision and upload everything to
+ * the context's device.  `kernel` is one of WDF_KERNEL_*; with AUTO or
+ * SPECIALISED the pattern/histogram/gather kernels are generated for this
+ * ensemble and compiled with hipRTC (cached per source).
+ * Errors: INVALID_ARG (cycles, bad child or feature index, n_features < 1),
+ * UNSUPPORTED (a path with more than WDF_MAX_DEPTH inner nodes, more than
+ * WDF_MAX_FEATURES features), COMPILE (SPECIALISED only), OOM, DEVICE. */
+int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out);
+void wdf_model_destroy(wdf_model *model);
+
+/* Per-group description of the model's layout (for tests and tools).  A group
+ * is a pair of sibling leaves or a single leaf whose sibling is an inner node.
+ * Any array may be NULL.  Returns the number of groups (>= 0) or an error. */
+int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32_t *depth, int64_t *leaf_left,
+                         int64_t *leaf_right, int64_t *hist_offset, int64_t *table_offset);
+
+/* 1 when the model runs the specialised kernels, 0 for the generic ones. */
+int wdf_model_specialised(const wdf_model *model);
+
+/* Summarise a background set: decision patterns of every row at every group,
+ * exact uint32 histograms, then (MFMA) the tables
+ *     t_q[k][p] = (w_l/m) (M h_l)[p] + (w_r/m) (M h_r)[p ^ 1]
+ * for the values selected by `values` (WDF_SHAPLEY / WDF_BANZHAF), and the base
+ * value mean_b f(b).  B is column-major (B[f * ldb + r]), m >= 1 rows, on the
+ * device when b_on_device is nonzero, else on the host (copied in).  Work is
+ * enqueued on `hip_stream` (NULL = the HIP null stream) and the call
+ * returns after it finishes, so B may be freed on return.  The summary owns
+ * all device state that wdf_explain needs (histograms, tables, workspace).
+ * Errors: INVALID_ARG, OOM, DEVICE. */
+int wdf_background_load(wdf_model *model, const float *B, int64_t m, int64_t ldb, int b_on_device,
+                        int values, void *hip_stream, wdf_bg **out);
+
+/* Path-Dependent variant (Section 8, Formula eq:path_dependent_estimation):
+ * the background histogram is replaced by the cover-product frequency of every
+ * pattern; the model must have been loaded with covers.  Same output handle. */
+int wdf_pathdep_load(wdf_model *model, int values, void *hip_stream, wdf_bg **out);
+
+void wdf_bg_destroy(wdf_bg *bg);
+
+/* phi[f * ldphi + r] = value of feature f for consumer row r, r < n.  X and phi
+ * are device pointers (column-major), n >= 0, ldx >= n, ldphi >= n.  Every
+ * feature row of phi in [0, n_features) is written (exact 0.0 for features no
+ * path uses).  Asynchronous on `hip_stream`; the caller keeps X and phi alive
+ * until the stream reaches this work.  Allocates nothing; read-only on bg, so
+ * concurrent calls on different streams are safe.
+ * Errors: INVALID_ARG, DEVICE. */
+int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi,
+                void *hip_stream);
+
+/* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
+ * f(c) - base).  For a path-dependent summary: the cover-weighted mean. */
+int wdf_base_value(const wdf_bg *bg, double *out);
+
+/* ---- debug / parity (not on the hot path) ------------------------------- */
+
+/* Decision patterns (Def. Decision Pattern, group orientation: the left leaf
+ * of a pair, the leaf itself for a single) of n device rows:
+ * out[g * n + r], uint32, device pointer.  Synchronous. */
+int wdf_debug_patterns(const wdf_model *model, const float *X, int64_t n, int64_t ldx, uint32_t *out,
+                       void *hip_stream);
+/* Copy the uint32 histograms (cap entries of host memory) / float tables /
+ * double tables to the host.  Returns the number of entries or an error. */
+int64_t wdf_debug_histograms(const wdf_bg *bg, uint32_t *host_out, int64_t cap);
+int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap);
+
+/* Model-specialised kernels without a device: lay out the ensemble, write the
+ * generated HIP source (returned in out, NUL-terminated, when cap is large
+ * enough; the return value is the source length) and, with compile != 0, also
+ * compile it for gfx950 with hipRTC (COMPILE on failure, the log in
+ * wdf_last_error()).  For tools and tests; needs no GPU. */
+int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int compile, char *out, int64_t cap);
+
+/* ---- serving: continuous batching of explain requests ------------------- */
+
+typedef struct wdf_server wdf_server;
+
+typedef struct {
+  uint64_t submitted, completed, rejected;
+  uint64_t batches;           /* device launches */
+  uint64_t rows;              /* rows explained */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result on host */
+  double busy_ms;             /* sum of device batch times */
+} wdf_stats;
+
+/* A server keeps bg resident, owns pinned staging slots totalling at most
+ * mem_budget bytes and a worker thread that forms batches of up to max_rows
+ * rows from queued requests, copies them in, runs wdf_explain and copies
+ * results out, overlapping consecutive batches on two streams.  Requests of
+ * 1..max_rows rows are admitted as slot memory frees up.
+ * Errors: INVALID_ARG (budget too small for one batch), OOM, DEVICE. */
+int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int queue_cap, wdf_server **out);
+/* Enqueue n rows of host X (column-major, ldx >= n); phi_host receives
+ * [n_features][n] column-major float32 when the ticket completes.  X is copied
+ * before return.  Errors: INVALID_ARG, BUSY (queue full). */
+int wdf_server_submit(wdf_server *srv, const float *X_host, int64_t n, int64_t ldx, float *phi_host,
+                      uint64_t *ticket);
+/* Wait until the ticket completes (timeout_ms < 0: forever).  Errors: TIMEOUT,
+ * INVALID_ARG (unknown ticket). */
+int wdf_server_wait(wdf_server *srv, uint64_t ticket, int timeout_ms);
+int wdf_server_stats(wdf_server *srv, wdf_stats *out);
+void wdf_server_destroy(wdf_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,622 @@
+// Host side of the C ABI declared in include/wdf.h: ensemble validation and
+// layout, coefficient matrices in double precision, background summaries and
+// the explain dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wdf.h"
+#include "wdf_dev.h"
+#include "wdf_internal.h"
+#include "wdf_impl.h"
+
+using namespace wdf;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+namespace wdf {
+int set_error(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+int hip_error(hipError_t e, const char *what) {
+  return set_error(WDF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace wdf
+
+extern "C" const char *wdf_last_error(void) { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_error(e_, #expr);  \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+
+namespace wdf {
+
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+int DevBuf::alloc(size_t n) {
+  reset();
+  if (n == 0) return WDF_OK;
+  hipError_t e = hipMalloc(&ptr, n);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(WDF_E_OOM, "hipMalloc(%zu bytes): %s", n, hipGetErrorString(e));
+  }
+  bytes = n;
+  return WDF_OK;
+}
+
+}  // namespace wdf
+
+// Copy a host vector into a fresh device buffer.  The copy completes before
+// return, so the vector may be a temporary.
+template <class T>
+static int upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
+  int rc = buf.alloc(v.size() * sizeof(T));
+  if (rc) return rc;
+  if (!v.empty()) {
+    HIP_TRY(hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return WDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+extern "C" int wdf_create(int device, wdf_ctx **out) {
+  if (!out) return set_error(WDF_E_INVALID_ARG, "wdf_create: out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count)
+    return set_error(WDF_E_INVALID_ARG, "wdf_create: device %d out of range (%d devices)", device, count);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(WDF_E_UNSUPPORTED, "wdf_create: device %d is %s; this library is built for gfx950", device,
+                     prop.gcnArchName);
+  std::unique_ptr<wdf_ctx> c(new (std::nothrow) wdf_ctx());
+  if (!c) return set_error(WDF_E_OOM, "wdf_create: out of host memory");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  *out = c.release();
+  return WDF_OK;
+}
+
+extern "C" void wdf_destroy(wdf_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient matrices (Section 5 four rules, Formulas shap_simplified_formula
+// and banzhaf_simplified_formula), for a path of d distinct features
+// ---------------------------------------------------------------------------
+
+static double binomial(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * double(n - k + i) / double(i);
+  return r;
+}
+
+// M[(k * 2^d + pc) * 2^d + pb] = value of the feature at path position k for the
+// cube of the pattern pair (pc, pb) with leaf weight 1.  A (0,0) position makes
+// the cube unsatisfiable (all zero); (1,0) gives a positive literal, (0,1) a
+// negated one, (1,1) no literal.
+static void build_coef_matrix(int d, int values, std::vector<double> &M) {
+  const int P = 1 << d;
+  M.assign((size_t)d * P * P, 0.0);
+  for (int pc = 0; pc < P; ++pc) {
+    for (int pb = 0; pb < P; ++pb) {
+      if (((~pc) & (~pb)) & (P - 1)) continue;  // some position with (0,0)
+      const int pos = __builtin_popcount(pc & ~pb & (P - 1));
+      const int neg = __builtin_popcount(~pc & pb & (P - 1));
+      const int s = pos + neg;
+      if (s == 0) continue;
+      double cp, cn;
+      if (values == WDF_BANZHAF) {
+        cp = std::ldexp(1.0, -(s - 1));
+        cn = -cp;
+      } else {
+        cp = pos ? 1.0 / (double(pos) * binomial(s, pos)) : 0.0;
+        cn = neg ? -1.0 / (double(neg) * binomial(s, neg)) : 0.0;
+      }
+      for (int k = 0; k < d; ++k) {
+        const int bit = d - 1 - k;
+        const int c = (pc >> bit) & 1, b = (pb >> bit) & 1;
+        double v = 0.0;
+        if (c && !b) v = cp;
+        else if (!c && b) v = cn;
+        M[((size_t)k * P + pc) * P + pb] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Model
+// ---------------------------------------------------------------------------
+
+int wdf::validate_and_layout(const wdf_model_desc *d, wdf_model *M) {
+  if (d->n_trees < 1) return set_error(WDF_E_INVALID_ARG, "model: n_trees must be >= 1");
+  if (d->n_features < 1) return set_error(WDF_E_INVALID_ARG, "model: n_features must be >= 1");
+  if (d->n_features > WDF_MAX_FEATURES)
+    return set_error(WDF_E_UNSUPPORTED, "model: %d features exceeds the limit %d", d->n_features, WDF_MAX_FEATURES);
+  if (!d->node_offset || !d->feature || !d->left || !d->right || !d->threshold || !d->value || !d->default_left)
+    return set_error(WDF_E_INVALID_ARG, "model: a required array is NULL");
+  if (d->node_offset[0] != 0) return set_error(WDF_E_INVALID_ARG, "model: node_offset[0] must be 0");
+  const int T = d->n_trees;
+  for (int t = 0; t < T; ++t)
+    if (d->node_offset[t + 1] <= d->node_offset[t])
+      return set_error(WDF_E_INVALID_ARG, "model: tree %d has no nodes", t);
+  const int64_t N = d->node_offset[T];
+  M->n_trees = T;
+  M->n_features = d->n_features;
+  M->n_nodes = N;
+  M->feature.assign(d->feature, d->feature + N);
+  M->left.assign(d->left, d->left + N);
+  M->right.assign(d->right, d->right + N);
+  M->threshold.assign(d->threshold, d->threshold + N);
+  M->value.assign(d->value, d->value + N);
+  M->default_left.assign(d->default_left, d->default_left + N);
+  M->node_offset.assign(d->node_offset, d->node_offset + T + 1);
+  M->has_cover = d->cover != nullptr;
+  if (M->has_cover) M->cover.assign(d->cover, d->cover + N);
+
+  // structure checks: every non-root node has exactly one parent, every node is
+  // reachable from the root, features in range, paths within the depth limit
+  for (int t = 0; t < T; ++t) {
+    const int64_t base = d->node_offset[t], nn = d->node_offset[t + 1] - base;
+    std::vector<int> parents((size_t)nn, 0), depth((size_t)nn, -1);
+    for (int64_t i = 0; i < nn; ++i) {
+      const int32_t f = d->feature[base + i], l = d->left[base + i], r = d->right[base + i];
+      if (f < 0) {
+        if (l != -1 || r != -1)
+          return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld is a leaf with children", t, (long long)i);
+        continue;
+      }
+      if (f >= d->n_features)
+        return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has feature %d >= n_features %d", t,
+                         (long long)i, f, d->n_features);
+      if (l <= 0 || r <= 0 || l >= nn || r >= nn || l == r)
+        return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has invalid children (%d, %d)", t,
+                         (long long)i, l, r);
+      parents[(size_t)l]++;
+      parents[(size_t)r]++;
+    }
+    for (int64_t i = 1; i < nn; ++i)
+      if (parents[(size_t)i] != 1)
+        return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has %d parents", t, (long long)i,
+                         parents[(size_t)i]);
+    if (parents[0] != 0) return set_error(WDF_E_INVALID_ARG, "model: tree %d root has a parent", t);
+    std::vector<int64_t> queue{0};
+    depth[0] = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int64_t i = queue[h];
+      if (d->feature[base + i] < 0) continue;
+      for (int32_t c : {d->left[base + i], d->right[base + i]}) {
+        if (depth[(size_t)c] >= 0) return set_error(WDF_E_INVALID_ARG, "model: tree %d has a cycle", t);
+        depth[(size_t)c] = depth[(size_t)i] + 1;
+        if (depth[(size_t)c] > WDF_MAX_DEPTH)
+          return set_error(WDF_E_UNSUPPORTED, "model: tree %d has a path with more than %d inner nodes", t,
+                           WDF_MAX_DEPTH);
+        queue.push_back(c);
+      }
+    }
+    if ((int64_t)queue.size() != nn)
+      return set_error(WDF_E_INVALID_ARG, "model: tree %d has %lld nodes unreachable from the root", t,
+                       (long long)(nn - (int64_t)queue.size()));
+  }
+
+  // groups in depth-first order per tree
+  M->tree_group_off.assign(1, 0);
+  for (int t = 0; t < T; ++t) {
+    const int64_t base = d->node_offset[t];
+    int64_t path_nodes[WDF_MAX_DEPTH + 1];
+    uint8_t path_dirs[WDF_MAX_DEPTH + 1];
+    auto emit = [&](int dep, int64_t leaf_l, int64_t leaf_r) {
+      Group g{};
+      g.tree = t;
+      g.depth = dep;
+      g.path_off = (int32_t)M->path.size();
+      g.w_l = d->value[leaf_l];
+      g.w_r = leaf_r >= 0 ? d->value[leaf_r] : 0.f;
+      g.col_l = -1;
+      g.col_r = leaf_r >= 0 ? 0 : -1;  // real columns assigned below
+      int32_t feats[WDF_MAX_DEPTH];
+      int dp = 0;
+      for (int k = 0; k < dep; ++k) {
+        const int64_t nd = path_nodes[k];
+        PathNode pn{};
+        pn.thr = d->threshold[nd];
+        pn.feat = d->feature[nd];
+        pn.dl = d->default_left[nd] ? 1 : 0;
+        pn.dir = path_dirs[k];
+        int found = -1;
+        for (int q = 0; q < dp; ++q)
+          if (feats[q] == pn.feat) found = q;
+        if (found < 0) {
+          feats[dp] = pn.feat;
+          pn.merge = (uint8_t)dp++;
+          pn.first = 1;
+        } else {
+          pn.merge = (uint8_t)found;
+          pn.first = 0;
+        }
+        M->path.push_back(pn);
+        M->path_nodes.push_back(nd);
+      }
+      g.dprime = dp;
+      M->groups.push_back(g);
+      M->group_leaf_l.push_back(leaf_l);
+      M->group_leaf_r.push_back(leaf_r);
+    };
+    // depth-first; a pair's pattern is its left leaf's (last direction 0)
+    std::function<void(int64_t, int)> visit = [&](int64_t local, int dep) {
+      const int64_t g = base + local;
+      if (d->feature[g] < 0) {
+        if (dep == 0) emit(0, g, -1);  // a tree that is a single leaf
+        return;
+      }
+      path_nodes[dep] = g;
+      const int64_t l = base + d->left[g], r = base + d->right[g];
+      const bool ll = d->feature[l] < 0, rl = d->feature[r] < 0;
+      if (ll && rl) {
+        path_dirs[dep] = 0;
+        emit(dep + 1, l, r);
+      } else {
+        if (ll) { path_dirs[dep] = 0; emit(dep + 1, l, -1); }
+        if (rl) { path_dirs[dep] = 1; emit(dep + 1, r, -1); }
+      }
+      if (!ll) { path_dirs[dep] = 0; visit(d->left[g], dep + 1); }
+      if (!rl) { path_dirs[dep] = 1; visit(d->right[g], dep + 1); }
+    };
+    visit(0, 0);
+    M->tree_group_off.push_back((int64_t)M->groups.size());
+  }
+
+  // histogram / table offsets and contraction columns per class
+  int64_t h = 0, tb = 0;
+  for (auto &g : M->groups) {
+    g.hist_off = h;
+    g.tab_off = tb;
+    h += (int64_t)1 << g.depth;
+    tb += (((int64_t)g.depth << g.depth) + 3) & ~(int64_t)3;  // 16-byte aligned tables
+    if (g.depth > 0) {
+      ClassInfo &c = M->cls[g.dprime];
+      g.col_l = c.ncols++;
+      g.col_r = (g.col_r >= 0) ? c.ncols++ : -1;
+    } else {
+      g.col_l = -1;
+      g.col_r = -1;
+    }
+  }
+  M->hist_size = h;
+  M->tab_size = tb;
+  int64_t ho = 0, so = 0;
+  for (int dp = 0; dp <= WDF_MAX_DEPTH; ++dp) {
+    ClassInfo &c = M->cls[dp];
+    c.h_off = ho;
+    c.s_off = so;
+    ho += (int64_t)c.ncols << dp;
+    so += (int64_t)c.ncols * dp << dp;
+  }
+  M->h_total = ho;
+  M->s_total = so;
+  return WDF_OK;
+}
+
+static int upload_model(wdf_model *M) {
+  hipStream_t s = M->ctx->stream;
+  int rc;
+  if ((rc = upload(M->d_groups, M->groups, s))) return rc;
+  if ((rc = upload(M->d_path, M->path, s))) return rc;
+  std::vector<int64_t> hoff(WDF_MAX_DEPTH + 1), soff(WDF_MAX_DEPTH + 1);
+  for (int dp = 0; dp <= WDF_MAX_DEPTH; ++dp) {
+    hoff[(size_t)dp] = M->cls[dp].h_off;
+    soff[(size_t)dp] = M->cls[dp].s_off;
+  }
+  if ((rc = upload(M->d_hclass_off, hoff, s))) return rc;
+  if ((rc = upload(M->d_sclass_off, soff, s))) return rc;
+  for (int values = 0; values < 2; ++values) {
+    for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
+      if (M->cls[dp].ncols == 0) continue;
+      std::vector<double> coef;
+      build_coef_matrix(dp, values, coef);
+      if ((rc = upload(M->d_coef[values][dp], coef, s))) return rc;
+    }
+  }
+  if (M->has_cover) {
+    // cover ratio of every path position: cover(next node) / cover(node)
+    std::vector<double> ratio(M->path.size(), 0.0);
+    for (size_t gi = 0; gi < M->groups.size(); ++gi) {
+      const Group &g = M->groups[gi];
+      for (int k = 0; k < g.depth; ++k) {
+        const int64_t nd = M->path_nodes[(size_t)g.path_off + k];
+        const int64_t base = M->node_offset[(size_t)g.tree];
+        int64_t nx;
+        if (k + 1 < g.depth) nx = M->path_nodes[(size_t)g.path_off + k + 1];
+        else nx = M->path[(size_t)g.path_off + k].dir ? base + M->right[(size_t)nd] : base + M->left[(size_t)nd];
+        const double cn = M->cover[(size_t)nd];
+        ratio[(size_t)g.path_off + k] = cn > 0 ? M->cover[(size_t)nx] / cn : 0.0;
+      }
+    }
+    if ((rc = upload(M->d_ratio, ratio, s))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return WDF_OK;
+}
+
+extern "C" int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out) {
+  if (!ctx || !desc || !out) return set_error(WDF_E_INVALID_ARG, "wdf_model_load: NULL argument");
+  *out = nullptr;
+  if (kernel < WDF_KERNEL_AUTO || kernel > WDF_KERNEL_SPECIALISED)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_load: unknown kernel choice %d", kernel);
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<wdf_model> M(new (std::nothrow) wdf_model());
+  if (!M) return set_error(WDF_E_OOM, "wdf_model_load: out of host memory");
+  M->ctx = ctx;
+  M->device = ctx->device;
+  int rc;
+  try {
+    if ((rc = validate_and_layout(desc, M.get()))) return rc;
+  } catch (const std::bad_alloc &) {
+    return set_error(WDF_E_OOM, "wdf_model_load: out of host memory");
+  }
+  if ((rc = upload_model(M.get()))) return rc;
+  if (kernel != WDF_KERNEL_GENERIC) {
+    rc = jit_build(M.get());
+    if (rc != WDF_OK) {
+      if (kernel == WDF_KERNEL_SPECIALISED) return rc;
+      M->jit.reset();  // AUTO: keep the generic kernels
+    }
+  }
+  *out = M.release();
+  return WDF_OK;
+}
+
+extern "C" void wdf_model_destroy(wdf_model *model) {
+  if (!model) return;
+  (void)hipSetDevice(model->device);
+  delete model;
+}
+
+extern "C" int wdf_model_specialised(const wdf_model *model) { return (model && model->jit) ? 1 : 0; }
+
+extern "C" int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32_t *depth, int64_t *leaf_left,
+                                    int64_t *leaf_right, int64_t *hist_offset, int64_t *table_offset) {
+  if (!model) return set_error(WDF_E_INVALID_ARG, "wdf_model_groups: NULL model");
+  const size_t G = model->groups.size();
+  for (size_t i = 0; i < G; ++i) {
+    const Group &g = model->groups[i];
+    if (tree) tree[i] = g.tree;
+    if (depth) depth[i] = g.depth;
+    if (leaf_left) leaf_left[i] = model->group_leaf_l[i];
+    if (leaf_right) leaf_right[i] = model->group_leaf_r[i];
+    if (hist_offset) hist_offset[i] = g.hist_off;
+    if (table_offset) table_offset[i] = g.tab_off;
+  }
+  return (int64_t)G;
+}
+
+// ---------------------------------------------------------------------------
+// Background summary: patterns -> histograms -> MFMA contraction -> tables
+// ---------------------------------------------------------------------------
+
+// NULL selects the HIP null stream, which orders with every blocking stream
+// (torch's default stream is the null stream).
+static hipStream_t pick_stream(wdf_ctx *, void *s) { return (hipStream_t)s; }
+
+// Columns, MFMA products per class, expansion into the gather tables, base value.
+static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
+                    hipStream_t s) {
+  DevBuf H, S, base;
+  int rc;
+  if ((rc = H.alloc((size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
+  if ((rc = S.alloc((size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
+  if ((rc = base.alloc(sizeof(double)))) return rc;
+  if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(M->tab_size, 1) * sizeof(float)))) return rc;
+  const int64_t G = (int64_t)M->groups.size();
+  HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));  // padding between tables
+  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
+                         M->d_hclass_off.as<int64_t>(), H.as<double>(), s));
+  for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
+    const ClassInfo &c = M->cls[dp];
+    if (c.ncols == 0) continue;
+    const int K = 1 << dp, R = dp * K;
+    HIP_TRY(launch_gemm_f64(M->d_coef[bg->values][dp].as<double>(), H.as<double>() + c.h_off,
+                            S.as<double>() + c.s_off, R, K, c.ncols, s));
+  }
+  HIP_TRY(launch_expand(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_sclass_off.as<int64_t>(),
+                        S.as<double>(), bg->d_tab.as<float>(), nullptr, s));
+  HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0,
+                      base.as<double>(), s));
+  HIP_TRY(hipMemcpyAsync(&bg->base, base.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return WDF_OK;
+}
+
+extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int64_t ldb, int b_on_device,
+                                   int values, void *hip_stream, wdf_bg **out) {
+  if (!M || !B || !out) return set_error(WDF_E_INVALID_ARG, "wdf_background_load: NULL argument");
+  *out = nullptr;
+  if (m < 1 || ldb < m) return set_error(WDF_E_INVALID_ARG, "wdf_background_load: need m >= 1 and ldb >= m");
+  if (m > 0xFFFFFFFFll) return set_error(WDF_E_UNSUPPORTED, "wdf_background_load: m exceeds uint32 counts");
+  if (values != WDF_SHAPLEY && values != WDF_BANZHAF)
+    return set_error(WDF_E_INVALID_ARG, "wdf_background_load: unknown value kind %d", values);
+  HIP_TRY(hipSetDevice(M->ctx->device));
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  std::unique_ptr<wdf_bg> bg(new (std::nothrow) wdf_bg());
+  if (!bg) return set_error(WDF_E_OOM, "wdf_background_load: out of host memory");
+  bg->model = M;
+  bg->device = M->device;
+  bg->m = m;
+  bg->values = values;
+  int rc;
+  DevBuf Bcopy;
+  const float *Bd = B;
+  if (!b_on_device) {
+    if ((rc = Bcopy.alloc((size_t)M->n_features * (size_t)m * sizeof(float)))) return rc;
+    HIP_TRY(hipMemcpy2DAsync(Bcopy.ptr, (size_t)m * sizeof(float), B, (size_t)ldb * sizeof(float),
+                             (size_t)m * sizeof(float), (size_t)M->n_features, hipMemcpyHostToDevice, s));
+    Bd = Bcopy.as<float>();
+    ldb = m;
+  }
+  if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(uint32_t)))) return rc;
+  HIP_TRY(hipMemsetAsync(bg->d_hist.ptr, 0, bg->d_hist.bytes, s));
+  if (M->jit) {
+    if ((rc = jit_hist(M, Bd, m, ldb, bg->d_hist.as<uint32_t>(), s))) return rc;
+  } else {
+    HIP_TRY(launch_hist_generic(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(), Bd,
+                                m, ldb, bg->d_hist.as<uint32_t>(), s));
+  }
+  if ((rc = contract(M, bg.get(), bg->d_hist.as<uint32_t>(), nullptr, 1.0 / (double)m, s))) return rc;
+  *out = bg.release();
+  return WDF_OK;
+}
+
+extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_bg **out) {
+  if (!M || !out) return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: NULL argument");
+  *out = nullptr;
+  if (!M->has_cover) return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: the model was loaded without covers");
+  if (values != WDF_SHAPLEY && values != WDF_BANZHAF)
+    return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: unknown value kind %d", values);
+  HIP_TRY(hipSetDevice(M->ctx->device));
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  std::unique_ptr<wdf_bg> bg(new (std::nothrow) wdf_bg());
+  if (!bg) return set_error(WDF_E_OOM, "wdf_pathdep_load: out of host memory");
+  bg->model = M;
+  bg->device = M->device;
+  bg->m = 0;
+  bg->values = values;
+  bg->pathdep = true;
+  int rc;
+  if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(double)))) return rc;
+  HIP_TRY(launch_pd_freq(M->d_groups.as<Group>(), (int64_t)M->groups.size(), M->d_ratio.as<double>(),
+                         bg->d_hist.as<double>(), s));
+  if ((rc = contract(M, bg.get(), nullptr, bg->d_hist.as<double>(), 1.0, s))) return rc;
+  *out = bg.release();
+  return WDF_OK;
+}
+
+extern "C" void wdf_bg_destroy(wdf_bg *bg) {
+  if (!bg) return;
+  (void)hipSetDevice(bg->device);
+  delete bg;
+}
+
+extern "C" int wdf_base_value(const wdf_bg *bg, double *out) {
+  if (!bg || !out) return set_error(WDF_E_INVALID_ARG, "wdf_base_value: NULL argument");
+  *out = bg->base;
+  return WDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Explain
+// ---------------------------------------------------------------------------
+
+extern "C" int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi,
+                           void *hip_stream) {
+  if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_explain: NULL summary");
+  if (n < 0 || ldx < n || ldphi < n) return set_error(WDF_E_INVALID_ARG, "wdf_explain: need 0 <= n <= ldx, ldphi");
+  if (n == 0) return WDF_OK;
+  if (!X || !phi) return set_error(WDF_E_INVALID_ARG, "wdf_explain: NULL X or phi");
+  wdf_model *M = bg->model;
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  if (M->jit) return jit_explain(bg, X, n, ldx, phi, ldphi, s);
+  HIP_TRY(launch_explain_generic(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(),
+                                 bg->d_tab.as<float>(), X, n, ldx, phi, ldphi, M->n_features, s));
+  return WDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Debug / parity
+// ---------------------------------------------------------------------------
+
+extern "C" int wdf_debug_patterns(const wdf_model *M, const float *X, int64_t n, int64_t ldx, uint32_t *out,
+                                  void *hip_stream) {
+  if (!M || (!X && n) || (!out && n)) return set_error(WDF_E_INVALID_ARG, "wdf_debug_patterns: NULL argument");
+  if (n < 0 || ldx < n) return set_error(WDF_E_INVALID_ARG, "wdf_debug_patterns: need 0 <= n <= ldx");
+  HIP_TRY(hipSetDevice(M->ctx->device));
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  HIP_TRY(launch_patterns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(), X, n, ldx,
+                          out, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return WDF_OK;
+}
+
+extern "C" int64_t wdf_debug_histograms(const wdf_bg *bg, uint32_t *host_out, int64_t cap) {
+  if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_debug_histograms: NULL summary");
+  if (bg->pathdep) return set_error(WDF_E_INVALID_ARG, "wdf_debug_histograms: path-dependent summary has no counts");
+  const int64_t n = bg->model->hist_size;
+  if (host_out) {
+    if (cap < n) return set_error(WDF_E_INVALID_ARG, "wdf_debug_histograms: capacity %lld < %lld", (long long)cap,
+                                  (long long)n);
+    HIP_TRY(hipSetDevice(bg->model->ctx->device));
+    HIP_TRY(hipMemcpy(host_out, bg->d_hist.ptr, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  }
+  return n;
+}
+
+extern "C" int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap) {
+  if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_debug_tables: NULL summary");
+  const int64_t n = bg->model->tab_size;
+  if (host_out) {
+    if (cap < n) return set_error(WDF_E_INVALID_ARG, "wdf_debug_tables: capacity %lld < %lld", (long long)cap,
+                                  (long long)n);
+    HIP_TRY(hipSetDevice(bg->model->ctx->device));
+    HIP_TRY(hipMemcpy(host_out, bg->d_tab.ptr, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  return n;
+}
+
+extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int do_compile, char *out, int64_t cap) {
+  if (!desc) return set_error(WDF_E_INVALID_ARG, "wdf_debug_specialised_source: NULL desc");
+  try {
+    wdf_model M;
+    int rc = validate_and_layout(desc, &M);
+    if (rc) return rc;
+    std::string src;
+    if ((rc = jit_source(&M, do_compile != 0, src))) return rc;
+    if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);
+    return (int64_t)src.size();
+  } catch (const std::bad_alloc &) {
+    return set_error(WDF_E_OOM, "wdf_debug_specialised_source: out of host memory");
+  }
+}

@@ -1,0 +1,116 @@
+// Internal state behind the opaque handles of include/wdf.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "wdf.h"
+#include "wdf_dev.h"
+
+namespace wdf {
+
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  int alloc(size_t n);
+  void reset();
+  template <class T>
+  T *as() const { return static_cast<T *>(ptr); }
+};
+
+struct JitModule;  // compiled model-specialised kernels (wdf_jit.cpp)
+
+// Layout of the model-specialised kernels (wdf_jit.cpp).
+struct JitPlan {
+  int wide = 0;                 // 0: 8-bit threshold ranks, 1: 16-bit
+  int per_word = 4;             // ranks packed per 32-bit word
+  int words = 0;                // words per row
+  std::vector<float> thr;       // sorted distinct thresholds, feature after feature
+  std::vector<int32_t> thr_off; // n_features + 1
+  std::vector<int32_t> rank;    // per node: index of its threshold among its feature's
+  int nt_hist = 512, nt_explain = 512;
+  int hist_cap = 32768;         // uint32 counters per histogram chunk (LDS)
+  int stage_floats = 12288;     // table floats per explain stage (LDS, double-buffered)
+  std::vector<std::pair<int64_t, int64_t>> hist_chunks;    // group ranges
+  std::vector<std::pair<int64_t, int64_t>> explain_stages; // group ranges
+  DevBuf d_thr, d_thr_off;
+};
+
+// Per-class contraction shape: paths with dprime distinct features.
+struct ClassInfo {
+  int ncols = 0;          // leaf columns in this class
+  int64_t h_off = 0;      // offset (doubles) of this class in the column buffer
+  int64_t s_off = 0;      // offset (doubles) of this class in the product buffer
+};
+
+}  // namespace wdf
+
+struct wdf_ctx {
+  int device = 0;
+  int n_cu = 0;
+  hipStream_t stream = nullptr;
+  std::mutex jit_mu;
+  std::map<std::string, std::shared_ptr<wdf::JitModule>> jit_cache;  // by generated source
+};
+
+struct wdf_model {
+  wdf_ctx *ctx = nullptr;
+  int device = 0;
+  int n_trees = 0, n_features = 0;
+  int64_t n_nodes = 0;
+  std::vector<int64_t> node_offset;
+  std::vector<int32_t> feature, left, right;
+  std::vector<float> threshold, value;
+  std::vector<uint8_t> default_left;
+  std::vector<double> cover;
+  bool has_cover = false;
+
+  // layout
+  std::vector<wdf::Group> groups;
+  std::vector<wdf::PathNode> path;
+  std::vector<int64_t> path_nodes;       // global node index of each PathNode
+  std::vector<int64_t> group_leaf_l, group_leaf_r;
+  std::vector<int64_t> tree_group_off;   // groups of tree t: [off[t], off[t+1])
+  int64_t hist_size = 0, tab_size = 0;
+  wdf::ClassInfo cls[WDF_MAX_DEPTH + 1];
+  int64_t h_total = 0, s_total = 0;
+
+  // device copies
+  wdf::DevBuf d_groups, d_path, d_hclass_off, d_sclass_off, d_ratio;
+  wdf::DevBuf d_coef[2][WDF_MAX_DEPTH + 1];  // [values][dprime]
+
+  // model-specialised kernels
+  std::shared_ptr<wdf::JitModule> jit;
+  wdf::JitPlan jp;
+};
+
+struct wdf_bg {
+  wdf_model *model = nullptr;
+  int device = 0;
+  int64_t m = 0;
+  int values = WDF_SHAPLEY;
+  bool pathdep = false;
+  double base = 0.0;
+  wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)
+  wdf::DevBuf d_tab;    // float gather tables
+};
+
+namespace wdf {
+// Model-specialised kernels (wdf_jit.cpp).
+int jit_build(wdf_model *M);
+int jit_source(wdf_model *M, bool do_compile, std::string &src);
+int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
+int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s);
+int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s);
+}  // namespace wdf

@@ -1,0 +1,28 @@
+// Internal declarations shared by the host code and the static kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wdf_dev.h"
+
+namespace wdf {
+
+hipError_t launch_hist_generic(const Group *groups, const PathNode *path, int64_t n_groups, const float *B,
+                               int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s);
+hipError_t launch_explain_generic(const Group *groups, const PathNode *path, int64_t n_groups, const float *tab,
+                                  const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, int F,
+                                  hipStream_t s);
+hipError_t launch_patterns(const Group *groups, const PathNode *path, int64_t n_groups, const float *X,
+                           int64_t n, int64_t ldx, uint32_t *out, hipStream_t s);
+hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_groups, const uint32_t *hist,
+                          const double *freq, double scale, const int64_t *class_off, double *H, hipStream_t s);
+hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s);
+hipError_t launch_expand(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *s_class_off,
+                         const double *S, float *tab, double *tab64, hipStream_t s);
+hipError_t launch_base(const Group *groups, int64_t n_groups, const uint32_t *hist, const double *freq,
+                       double scale, double *out, hipStream_t s);
+hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, double *freq, hipStream_t s);
+hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr, const int32_t *thr_off,
+                           int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s);
+
+}  // namespace wdf

@@ -1,0 +1,492 @@
+// Model-specialised kernels.
+//
+// For a given ensemble this file writes the pattern/histogram kernel and the
+// pattern/gather kernel as straight-line HIP code in which every node's
+// feature, threshold rank and default direction, every table offset and every
+// output feature is a compile-time constant, then compiles them with hipRTC
+// for gfx950.  A row's threshold ranks (8 or 16 bits per feature, packed in
+// 32-bit words) and its phi accumulators live in registers with static
+// indices; one node costs a byte-select compare and an add-with-carry that
+// shifts the path pattern (Alg. 1: P[left] = 2 P + split, P[right] = P[left] ^ 1).
+// Gather tables stream through LDS in double-buffered stages with direct
+// global-to-LDS loads.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "wdf.h"
+#include "wdf_dev.h"
+#include "wdf_impl.h"
+#include "wdf_internal.h"
+
+namespace wdf {
+
+struct JitModule {
+  hipModule_t mod = nullptr;
+  hipFunction_t hist = nullptr, explain = nullptr;
+  ~JitModule() {
+    if (mod) (void)hipModuleUnload(mod);
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Plan: threshold ranks, histogram chunks, explain stages
+// ---------------------------------------------------------------------------
+
+int make_plan(wdf_model *M) {
+  JitPlan &P = M->jp;
+  const int F = M->n_features;
+  std::vector<std::vector<float>> per(F);
+  for (int64_t i = 0; i < M->n_nodes; ++i) {
+    const int32_t f = M->feature[(size_t)i];
+    if (f < 0) continue;
+    const float t = M->threshold[(size_t)i];
+    if (std::isnan(t)) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: NaN threshold at node %lld", (long long)i);
+    per[(size_t)f].push_back(t);
+  }
+  size_t maxk = 0;
+  P.thr.clear();
+  P.thr_off.assign((size_t)F + 1, 0);
+  for (int f = 0; f < F; ++f) {
+    auto &v = per[(size_t)f];
+    std::sort(v.begin(), v.end());
+    // distinct values; -0.0 and +0.0 compare equal and count once
+    std::vector<float> u;
+    for (float t : v)
+      if (u.empty() || !(u.back() == t)) u.push_back(t);
+    maxk = std::max(maxk, u.size());
+    P.thr.insert(P.thr.end(), u.begin(), u.end());
+    P.thr_off[(size_t)f + 1] = (int32_t)P.thr.size();
+  }
+  if (maxk <= 127) {
+    P.wide = 0;
+    P.per_word = 4;
+  } else if (maxk <= 32767) {
+    P.wide = 1;
+    P.per_word = 2;
+  } else {
+    return set_error(WDF_E_UNSUPPORTED, "specialised kernels: a feature has %zu distinct thresholds", maxk);
+  }
+  P.words = (F + P.per_word - 1) / P.per_word;
+  P.rank.assign((size_t)M->n_nodes, -1);
+  for (int64_t i = 0; i < M->n_nodes; ++i) {
+    const int32_t f = M->feature[(size_t)i];
+    if (f < 0) continue;
+    const float *b = P.thr.data() + P.thr_off[(size_t)f];
+    const float *e = P.thr.data() + P.thr_off[(size_t)f + 1];
+    P.rank[(size_t)i] = (int32_t)(std::lower_bound(b, e, M->threshold[(size_t)i]) - b);
+  }
+  // histogram chunks: consecutive groups whose counters fit the LDS budget
+  P.hist_chunks.clear();
+  const int64_t G = (int64_t)M->groups.size();
+  for (int64_t g = 0; g < G;) {
+    int64_t a = g, size = 0;
+    while (g < G && size + ((int64_t)1 << M->groups[(size_t)g].depth) <= P.hist_cap) {
+      size += (int64_t)1 << M->groups[(size_t)g].depth;
+      ++g;
+    }
+    if (g == a) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: histogram chunk too small");
+    P.hist_chunks.push_back({a, g});
+  }
+  // explain stages: consecutive groups whose tables fit one LDS buffer
+  P.explain_stages.clear();
+  for (int64_t g = 0; g < G;) {
+    int64_t a = g;
+    const int64_t t0 = M->groups[(size_t)g].tab_off;
+    while (g < G) {
+      const Group &gg = M->groups[(size_t)g];
+      const int64_t end = gg.tab_off + (((int64_t)gg.depth << gg.depth) + 3) / 4 * 4;
+      if (end - t0 > P.stage_floats) break;
+      ++g;
+    }
+    if (g == a) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: explain stage too small");
+    P.explain_stages.push_back({a, g});
+  }
+  return WDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Source generation
+// ---------------------------------------------------------------------------
+
+const char *kPreamble = R"(
+typedef unsigned int u32;
+typedef long long i64;
+// node test on a threshold rank (unsigned: NaN goes right; signed: NaN goes left),
+// then pattern update P' = 2 P + split through the carry
+#define ND(po, pi, w, sel, j) asm("v_cmp_le_u32_sdwa vcc, %1, %2 src0_sel:" sel " src1_sel:DWORD\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc" : "=v"(po) : "v"(w), "s"(j), "v"(pi) : "vcc")
+#define NDS(po, pi, w, sel, j) asm("v_cmp_le_i32_sdwa vcc, sext(%1), %2 src0_sel:" sel " src1_sel:DWORD\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc" : "=v"(po) : "v"(w), "s"(j), "v"(pi) : "vcc")
+)";
+
+struct TreeIndex {
+  // per global node: group indices hanging off it, and the group range below it
+  std::vector<int64_t> pair_of, single_l, single_r, gmin, gmax;
+  std::vector<int64_t> root_leaf_group;  // per tree, -1 if the root is inner
+};
+
+TreeIndex index_tree_groups(const wdf_model *M) {
+  TreeIndex ix;
+  const size_t N = (size_t)M->n_nodes;
+  ix.pair_of.assign(N, -1);
+  ix.single_l.assign(N, -1);
+  ix.single_r.assign(N, -1);
+  ix.gmin.assign(N, INT64_MAX);
+  ix.gmax.assign(N, -1);
+  ix.root_leaf_group.assign((size_t)M->n_trees, -1);
+  for (size_t g = 0; g < M->groups.size(); ++g) {
+    const Group &gr = M->groups[g];
+    if (gr.depth == 0) {
+      ix.root_leaf_group[(size_t)gr.tree] = (int64_t)g;
+      continue;
+    }
+    const size_t last = (size_t)gr.path_off + (size_t)gr.depth - 1;
+    const int64_t parent = M->path_nodes[last];
+    if (gr.col_r >= 0) ix.pair_of[(size_t)parent] = (int64_t)g;
+    else if (M->path[last].dir == 0) ix.single_l[(size_t)parent] = (int64_t)g;
+    else ix.single_r[(size_t)parent] = (int64_t)g;
+    for (int k = 0; k < gr.depth; ++k) {
+      const size_t nd = (size_t)M->path_nodes[(size_t)gr.path_off + k];
+      ix.gmin[nd] = std::min<int64_t>(ix.gmin[nd], (int64_t)g);
+      ix.gmax[nd] = std::max<int64_t>(ix.gmax[nd], (int64_t)g);
+    }
+  }
+  return ix;
+}
+
+struct Gen {
+  const wdf_model *M;
+  const TreeIndex &ix;
+  std::ostringstream o;
+  int64_t a = 0, b = 0;  // group range being emitted
+  std::function<void(int64_t g, const std::string &p)> on_group;
+
+  std::string sel(int f) const {
+    const JitPlan &P = M->jp;
+    const int s = f % P.per_word;
+    if (P.wide) return s ? "\"WORD_1\"" : "\"WORD_0\"";
+    static const char *B[4] = {"\"BYTE_0\"", "\"BYTE_1\"", "\"BYTE_2\"", "\"BYTE_3\""};
+    return B[s];
+  }
+
+  // depth-first over the nodes whose subtree holds groups of [a, b)
+  void node(int64_t nd, const std::string &pin) {
+    if (!(ix.gmin[(size_t)nd] < b && ix.gmax[(size_t)nd] >= a)) return;
+    const int f = M->feature[(size_t)nd];
+    const int j = M->jp.rank[(size_t)nd];
+    const std::string pl = "p" + std::to_string(nd);
+    o << "u32 " << pl << "; " << (M->default_left[(size_t)nd] ? "NDS(" : "ND(") << pl << ", " << pin << ", w"
+      << f / M->jp.per_word << ", " << sel(f) << ", " << j << ");\n";
+    const int64_t base = M->node_offset[(size_t)M->groups[(size_t)ix.gmin[(size_t)nd]].tree];
+    const int64_t L = base + M->left[(size_t)nd], R = base + M->right[(size_t)nd];
+    auto in = [&](int64_t g) { return g >= a && g < b; };
+    if (ix.pair_of[(size_t)nd] >= 0) {
+      if (in(ix.pair_of[(size_t)nd])) on_group(ix.pair_of[(size_t)nd], pl);
+      return;
+    }
+    if (ix.single_l[(size_t)nd] >= 0 && in(ix.single_l[(size_t)nd])) on_group(ix.single_l[(size_t)nd], pl);
+    if (ix.single_r[(size_t)nd] >= 0 && in(ix.single_r[(size_t)nd]))
+      on_group(ix.single_r[(size_t)nd], "(" + pl + " ^ 1u)");
+    if (M->feature[(size_t)L] >= 0) node(L, pl);
+    if (M->feature[(size_t)R] >= 0 && ix.gmin[(size_t)R] < b && ix.gmax[(size_t)R] >= a) {
+      o << "u32 q" << nd << " = " << pl << " ^ 1u;\n";
+      node(R, "q" + std::to_string(nd));
+    }
+  }
+
+  // every tree touching [a, b)
+  void range(int64_t ga, int64_t gb) {
+    a = ga;
+    b = gb;
+    const int t0 = M->groups[(size_t)ga].tree, t1 = M->groups[(size_t)gb - 1].tree;
+    for (int t = t0; t <= t1; ++t) {
+      const int64_t root = M->node_offset[(size_t)t];
+      if (M->feature[(size_t)root] < 0) continue;
+      // `live` is always 1; the branch only splits the code into one basic
+      // block per tree, which keeps instruction selection time linear
+      o << "if (live) {\n";
+      node(root, "zero");
+      o << "}\n";
+    }
+  }
+};
+
+std::vector<int> used_words(const wdf_model *M, const TreeIndex &ix, int64_t a, int64_t b) {
+  std::vector<char> u((size_t)M->jp.words, 0);
+  for (int64_t g = a; g < b; ++g) {
+    const Group &gr = M->groups[(size_t)g];
+    for (int k = 0; k < gr.depth; ++k)
+      u[(size_t)(M->path[(size_t)gr.path_off + k].feat / M->jp.per_word)] = 1;
+  }
+  (void)ix;
+  std::vector<int> out;
+  for (int w = 0; w < M->jp.words; ++w)
+    if (u[(size_t)w]) out.push_back(w);
+  return out;
+}
+
+std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
+  const JitPlan &P = M->jp;
+  Gen gen{M, ix};
+  std::ostringstream &o = gen.o;
+  o << kPreamble;
+  o << "extern \"C\" __global__ __launch_bounds__(" << P.nt_hist
+    << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 rows_per_block, u32* __restrict__ hist, int live) {\n"
+    << "  __shared__ u32 lh[" << P.hist_cap << "];\n"
+    << "  const i64 r0 = (i64)blockIdx.x * rows_per_block;\n"
+    << "  i64 r1 = r0 + rows_per_block; if (r1 > m) r1 = m;\n"
+    << "  const u32 zero = 0u;\n"
+    << "  switch (blockIdx.y) {\n";
+  for (size_t c = 0; c < P.hist_chunks.size(); ++c) {
+    const int64_t a = P.hist_chunks[c].first, b = P.hist_chunks[c].second;
+    const int64_t h0 = M->groups[(size_t)a].hist_off;
+    const int64_t h1 = M->groups[(size_t)b - 1].hist_off + ((int64_t)1 << M->groups[(size_t)b - 1].depth);
+    o << "  case " << c << ": {\n"
+      << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist << ") lh[i] = 0u;\n"
+      << "    __syncthreads();\n"
+      << "    for (i64 row = r0 + threadIdx.x; row < r1; row += " << P.nt_hist << ") {\n";
+    for (int w : used_words(M, ix, a, b)) o << "      const u32 w" << w << " = codes[" << w << " * ldc + row];\n";
+    gen.on_group = [&](int64_t g, const std::string &p) {
+      o << "atomicAdd(&lh[" << (M->groups[(size_t)g].hist_off - h0) << " + " << p << "], 1u);\n";
+    };
+    gen.range(a, b);
+    o << "    }\n"
+      << "    __syncthreads();\n"
+      << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist
+      << ") { const u32 v = lh[i]; if (v) atomicAdd(&hist[" << h0 << " + i], v); }\n";
+    for (int64_t g = a; g < b; ++g)
+      if (M->groups[(size_t)g].depth == 0)
+        o << "    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&hist[" << M->groups[(size_t)g].hist_off
+          << "], (u32)m);\n";
+    o << "  } break;\n";
+  }
+  o << "  default: break;\n  }\n}\n";
+  return o.str();
+}
+
+std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
+  const JitPlan &P = M->jp;
+  const int F = M->n_features;
+  Gen gen{M, ix};
+  std::ostringstream &o = gen.o;
+  std::vector<char> used((size_t)F, 0);
+  for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
+  o << kPreamble;
+  o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n";
+  o << R"(
+__device__ __forceinline__ void stage_copy(const float* __restrict__ src, float* dst, int n16) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave * 64; c < n16; c += NT) {
+    if (c + lane < n16)
+      __builtin_amdgcn_global_load_lds((const void*)(src + 4 * (c + lane)),
+                                       (__attribute__((address_space(3))) void*)(dst + 4 * c), 16, 0, 0);
+  }
+}
+// codes and phi may share memory: each block reads its rows' codes before it
+// writes its rows' values, so neither pointer is restrict-qualified.
+extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const u32* codes, i64 ldc, const float* __restrict__ tab,
+                                                                  float* phi, i64 ldphi, i64 n, int live) {
+  __shared__ __attribute__((aligned(16))) float lds[2 * SF];
+  const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
+  const i64 rr = row < n ? row : n - 1;
+  const u32 zero = 0u;
+)";
+  for (int w = 0; w < P.words; ++w) {
+    bool any = false;
+    for (int s = 0; s < P.per_word; ++s)
+      if (w * P.per_word + s < F && used[(size_t)(w * P.per_word + s)]) any = true;
+    if (any) o << "  const u32 w" << w << " = codes[" << w << " * ldc + rr];\n";
+  }
+  for (int f = 0; f < F; ++f)
+    if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
+  const auto &S = P.explain_stages;
+  auto stage_span = [&](size_t s, int64_t &t0, int64_t &n16) {
+    const Group &ga = M->groups[(size_t)S[s].first];
+    const Group &gb = M->groups[(size_t)S[s].second - 1];
+    t0 = ga.tab_off;
+    const int64_t t1 = gb.tab_off + (((int64_t)gb.depth << gb.depth) + 3) / 4 * 4;
+    n16 = (t1 - t0) / 4;
+  };
+  int64_t t0, n16;
+  stage_span(0, t0, n16);
+  o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n"
+    << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
+  for (size_t s = 0; s < S.size(); ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < S.size()) {
+      stage_span(s + 1, t0, n16);
+      o << "  stage_copy(tab + " << t0 << ", lds + " << ((1 - buf) * P.stage_floats) << ", " << n16 << ");\n";
+    }
+    const int64_t sbase = M->groups[(size_t)S[s].first].tab_off;
+    gen.on_group = [&](int64_t g, const std::string &p) {
+      const Group &gr = M->groups[(size_t)g];
+      o << "{ const float* t = lds + " << (buf * P.stage_floats + (gr.tab_off - sbase)) << " + " << p << ";";
+      for (int k = 0; k < gr.depth; ++k) {
+        const PathNode &pn = M->path[(size_t)gr.path_off + k];
+        if (!pn.first) continue;
+        o << " f" << pn.feat << " += t[" << ((int64_t)k << gr.depth) << "];";
+      }
+      o << " }\n";
+    };
+    o << "  {\n";
+    gen.range(S[s].first, S[s].second);
+    o << "  }\n";
+    // keep each stage's accumulations inside the stage: without this the adds
+    // sink to the final (conditional) stores and every gathered value stays live
+    std::vector<char> touched((size_t)F, 0);
+    for (int64_t g = S[s].first; g < S[s].second; ++g) {
+      const Group &gr = M->groups[(size_t)g];
+      for (int k = 0; k < gr.depth; ++k)
+        if (M->path[(size_t)gr.path_off + k].first) touched[(size_t)M->path[(size_t)gr.path_off + k].feat] = 1;
+    }
+    for (int f = 0; f < F; ++f)
+      if (touched[(size_t)f]) o << "  asm volatile(\"\" : \"+v\"(f" << f << "));\n";
+    if (s + 1 < S.size()) o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
+  }
+  o << "  if (row < n) {\n";
+  for (int f = 0; f < F; ++f) o << "    phi[" << f << " * ldphi + row] = " << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ";\n";
+  o << "  }\n}\n";
+  return o.str();
+}
+
+// ---------------------------------------------------------------------------
+// hipRTC
+// ---------------------------------------------------------------------------
+
+int compile(const std::string &src, std::vector<char> &code) {
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "wdf_spec.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return set_error(WDF_E_COMPILE, "hiprtcCreateProgram failed");
+  const char *opts[] = {"--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    if (log.size() > 800) log = log.substr(0, 800);
+    return set_error(WDF_E_COMPILE, "hipRTC: %s: %s", hiprtcGetErrorString(r), log.c_str());
+  }
+  size_t sz = 0;
+  hiprtcGetCodeSize(prog, &sz);
+  code.resize(sz);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  return WDF_OK;
+}
+
+}  // namespace
+
+int jit_source(wdf_model *M, bool do_compile, std::string &src) {
+  int rc = make_plan(M);
+  if (rc) return rc;
+  const TreeIndex ix = index_tree_groups(M);
+  src = gen_hist(M, ix) + "\n" + gen_explain(M, ix).substr(std::strlen(kPreamble));
+  if (do_compile) {
+    std::vector<char> code;
+    if ((rc = compile(src, code))) return rc;
+  }
+  return WDF_OK;
+}
+
+// Limits beyond which the generated code would be too large to be worth it.
+static const int64_t kMaxSpecialisedNodes = 200000;
+
+int jit_build(wdf_model *M) {
+  if (M->n_nodes > kMaxSpecialisedNodes)
+    return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %lld nodes exceeds %lld", (long long)M->n_nodes,
+                     (long long)kMaxSpecialisedNodes);
+  std::string src;
+  int rc = jit_source(M, false, src);
+  if (rc) return rc;
+  std::shared_ptr<JitModule> mod;
+  {
+    std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
+    auto it = M->ctx->jit_cache.find(src);
+    if (it != M->ctx->jit_cache.end()) mod = it->second;
+  }
+  if (!mod) {
+    std::vector<char> code;
+    if ((rc = compile(src, code))) return rc;
+    auto m = std::make_shared<JitModule>();
+    hipError_t e = hipModuleLoadData(&m->mod, code.data());
+    if (e != hipSuccess) return hip_error(e, "hipModuleLoadData");
+    if ((e = hipModuleGetFunction(&m->hist, m->mod, "wdf_hist_spec")) != hipSuccess)
+      return hip_error(e, "hipModuleGetFunction(wdf_hist_spec)");
+    if ((e = hipModuleGetFunction(&m->explain, m->mod, "wdf_explain_spec")) != hipSuccess)
+      return hip_error(e, "hipModuleGetFunction(wdf_explain_spec)");
+    std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
+    M->ctx->jit_cache[src] = m;
+    mod = m;
+  }
+  JitPlan &P = M->jp;
+  hipStream_t s = M->ctx->stream;
+  if ((rc = P.d_thr.alloc(std::max<size_t>(P.thr.size(), 1) * sizeof(float)))) return rc;
+  if ((rc = P.d_thr_off.alloc(P.thr_off.size() * sizeof(int32_t)))) return rc;
+  hipError_t e;
+  if (!P.thr.empty() &&
+      (e = hipMemcpyAsync(P.d_thr.ptr, P.thr.data(), P.thr.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(thresholds)");
+  if ((e = hipMemcpyAsync(P.d_thr_off.ptr, P.thr_off.data(), P.thr_off.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(threshold offsets)");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  M->jit = mod;
+  return WDF_OK;
+}
+
+int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s) {
+  const JitPlan &P = M->jp;
+  DevBuf codes;
+  int rc;
+  if ((rc = codes.alloc((size_t)P.words * (size_t)m * sizeof(uint32_t)))) return rc;
+  hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr.as<float>(), P.d_thr_off.as<int32_t>(), P.wide,
+                                 P.words, codes.as<uint32_t>(), m, s);
+  if (e != hipSuccess) return hip_error(e, "quantize");
+  const int chunks = (int)P.hist_chunks.size();
+  int64_t blocks = std::max<int64_t>(1, (2 * (int64_t)M->ctx->n_cu + chunks - 1) / chunks);
+  blocks = std::min<int64_t>(blocks, (m + P.nt_hist - 1) / P.nt_hist);
+  int64_t rows_per_block = (m + blocks - 1) / blocks;
+  blocks = (m + rows_per_block - 1) / rows_per_block;
+  const uint32_t *cp = codes.as<uint32_t>();
+  int64_t ldc = m;
+  int live = 1;
+  void *args[] = {(void *)&cp, &ldc, &m, &rows_per_block, &hist, &live};
+  e = hipModuleLaunchKernel(M->jit->hist, (unsigned)blocks, (unsigned)chunks, 1, (unsigned)P.nt_hist, 1, 1, 0, s, args,
+                            nullptr);
+  if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(hist)");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hist");
+  return WDF_OK;
+}
+
+int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s) {
+  const wdf_model *M = bg->model;
+  const JitPlan &P = M->jp;
+  // threshold ranks go into the first rows of phi; the explain kernel reads a
+  // block's ranks before it writes that block's values
+  hipError_t e = launch_quantize(X, n, ldx, M->n_features, P.d_thr.as<float>(), P.d_thr_off.as<int32_t>(), P.wide,
+                                 P.words, reinterpret_cast<uint32_t *>(phi), ldphi, s);
+  if (e != hipSuccess) return hip_error(e, "quantize");
+  const uint32_t *cp = reinterpret_cast<const uint32_t *>(phi);
+  const float *tab = bg->d_tab.as<float>();
+  int live = 1;
+  void *args[] = {(void *)&cp, &ldphi, (void *)&tab, &phi, &ldphi, &n, &live};
+  const unsigned blocks = (unsigned)((n + P.nt_explain - 1) / P.nt_explain);
+  e = hipModuleLaunchKernel(M->jit->explain, blocks, 1, 1, (unsigned)P.nt_explain, 1, 1, 0, s, args, nullptr);
+  if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(explain)");
+  return WDF_OK;
+}
+
+}  // namespace wdf

@@ -1,0 +1,339 @@
+// Static kernels: the generic (data-driven) pattern, histogram and gather path,
+// the MFMA contraction of coefficient matrices with background histograms,
+// and the small bookkeeping kernels around it.  Model-specialised versions of
+// the pattern/histogram/gather kernels are generated at load time (wdf_jit.cpp).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wdf_dev.h"
+#include "wdf_internal.h"
+
+namespace wdf {
+
+// Def. Decision Tree: split(c) is True iff c_f < theta (True goes left); a
+// NaN value takes the node's default direction.
+__device__ __forceinline__ bool goes_left(float x, float thr, uint8_t dl) {
+  return (x != x) ? (dl != 0) : (x < thr);
+}
+
+// Def. Decision Pattern along a group's path; the root's bit is the MSB.
+__device__ __forceinline__ uint32_t group_pattern(const Group &g, const PathNode *__restrict__ path,
+                                                  const float *__restrict__ X, int64_t ldx, int64_t r) {
+  uint32_t p = 0;
+  for (int k = 0; k < g.depth; ++k) {
+    const PathNode nd = path[g.path_off + k];
+    const float x = X[(int64_t)nd.feat * ldx + r];
+    const bool left = goes_left(x, nd.thr, nd.dl);
+    p = (p << 1) | ((left == (nd.dir == 0)) ? 1u : 0u);
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Generic path
+// ---------------------------------------------------------------------------
+
+constexpr int kGroupsPerBlock = 64;
+
+__global__ __launch_bounds__(256) void k_hist_generic(const Group *__restrict__ groups,
+                                                      const PathNode *__restrict__ path, int64_t n_groups,
+                                                      const float *__restrict__ B, int64_t m, int64_t ldb,
+                                                      uint32_t *__restrict__ hist) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= m) return;
+  const int64_t g0 = (int64_t)blockIdx.y * kGroupsPerBlock;
+  const int64_t g1 = g0 + kGroupsPerBlock < n_groups ? g0 + kGroupsPerBlock : n_groups;
+  for (int64_t gi = g0; gi < g1; ++gi) {
+    const Group g = groups[gi];
+    const uint32_t p = group_pattern(g, path, B, ldb, r);
+    atomicAdd(&hist[g.hist_off + p], 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_explain_generic(const Group *__restrict__ groups,
+                                                         const PathNode *__restrict__ path, int64_t n_groups,
+                                                         const float *__restrict__ tab,
+                                                         const float *__restrict__ X, int64_t n, int64_t ldx,
+                                                         float *__restrict__ phi, int64_t ldphi, int F) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  for (int f = 0; f < F; ++f) phi[(int64_t)f * ldphi + r] = 0.f;
+  for (int64_t gi = 0; gi < n_groups; ++gi) {
+    const Group g = groups[gi];
+    if (g.depth == 0) continue;
+    const uint32_t p = group_pattern(g, path, X, ldx, r);
+    const float *t = tab + g.tab_off + p;
+    for (int k = 0; k < g.depth; ++k) {
+      const PathNode nd = path[g.path_off + k];
+      if (!nd.first) continue;
+      float *dst = phi + (int64_t)nd.feat * ldphi + r;
+      *dst += t[(int64_t)k << g.depth];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_patterns(const Group *__restrict__ groups,
+                                                  const PathNode *__restrict__ path, int64_t n_groups,
+                                                  const float *__restrict__ X, int64_t n, int64_t ldx,
+                                                  uint32_t *__restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const int64_t gi = blockIdx.y;
+  out[gi * n + r] = group_pattern(groups[gi], path, X, ldx, r);
+}
+
+// ---------------------------------------------------------------------------
+// Contraction: columns, MFMA product, expansion into the gather tables
+// ---------------------------------------------------------------------------
+
+// Merge a path pattern over its distinct features: the merged bit of a feature
+// is the AND of the bits of all path positions carrying it (a repeated feature
+// acts as one node whose condition is the intersection of the conditions).
+__device__ __forceinline__ uint32_t merge_pattern(const PathNode *__restrict__ pn, int d, int dp, uint32_t p) {
+  uint32_t merged = (1u << dp) - 1u;
+  for (int k = 0; k < d; ++k) {
+    const uint32_t bit = (p >> (d - 1 - k)) & 1u;
+    if (!bit) merged &= ~(1u << (dp - 1 - pn[k].merge));
+  }
+  return merged;
+}
+
+// H_{d'}[col][p'] = w * scale * sum over patterns p merging to p' of count[p];
+// the right leaf of a pair sees count[p ^ 1] (its pattern is the left's with
+// the last bit flipped).  `counts` is uint32 (background) or double (freq).
+__global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ groups,
+                                                 const PathNode *__restrict__ path,
+                                                 const uint32_t *__restrict__ hist,
+                                                 const double *__restrict__ freq, double scale,
+                                                 const int64_t *__restrict__ class_off,
+                                                 double *__restrict__ H) {
+  const Group g = groups[blockIdx.x];
+  if (g.depth == 0) return;
+  const int d = g.depth, dp = g.dprime;
+  const uint32_t K = 1u << dp;
+  const PathNode *pn = path + g.path_off;
+  double *Hc = H + class_off[dp];
+  for (uint32_t pp = threadIdx.x; pp < K; pp += blockDim.x) {
+    double sl = 0.0, sr = 0.0;
+    for (uint32_t p = 0; p < (1u << d); ++p) {
+      const double c = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
+      if (merge_pattern(pn, d, dp, p) == pp) sl += c;
+      if (g.col_r >= 0 && merge_pattern(pn, d, dp, p ^ 1u) == pp) sr += c;
+    }
+    Hc[(int64_t)g.col_l * K + pp] = sl * (double)g.w_l * scale;
+    if (g.col_r >= 0) Hc[(int64_t)g.col_r * K + pp] = sr * (double)g.w_r * scale;
+  }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// S[col][r] = sum_k M[r][k] * H[col][k]  (M: R x K row-major, H: ncols x K).
+// One wave per 16x16 tile of the output, v_mfma_f64_16x16x4f64 over K.
+__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ M, const double *__restrict__ H,
+                                                  double *__restrict__ S, int R, int K, int ncols) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int tiles_r = (R + 15) >> 4, tiles_c = (ncols + 15) >> 4;
+  if (wave >= tiles_r * tiles_c) return;  // uniform per wave
+  const int tr = wave % tiles_r, tc = wave / tiles_r;
+  const int i = lane & 15, kq = lane >> 4;
+  const int arow = tr * 16 + i, bcol = tc * 16 + i;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + kq;
+    const double a = (arow < R && kk < K) ? M[(int64_t)arow * K + kk] : 0.0;
+    const double b = (bcol < ncols && kk < K) ? H[(int64_t)bcol * K + kk] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  // output element (row 4*t + lane/16, column lane%16) sits in acc[t]
+  const int ccol = tc * 16 + (lane & 15);
+  const int rbase = tr * 16 + (lane >> 4);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int rr = rbase + 4 * t;
+    if (rr < R && ccol < ncols) S[(int64_t)ccol * R + rr] = acc[t];
+  }
+}
+
+// tab[g][k][p] = S_l[merge(k)][g(p)] + S_r[merge(k)][g(p ^ 1)] at the first
+// position of each feature on the path, 0 at later repeats.
+__global__ __launch_bounds__(256) void k_expand(const Group *__restrict__ groups,
+                                                const PathNode *__restrict__ path,
+                                                const int64_t *__restrict__ s_class_off,
+                                                const double *__restrict__ S, float *__restrict__ tab,
+                                                double *__restrict__ tab64) {
+  const Group g = groups[blockIdx.x];
+  if (g.depth == 0) return;
+  const int d = g.depth, dp = g.dprime;
+  const int64_t K = 1 << dp, R = (int64_t)dp * K;
+  const PathNode *pn = path + g.path_off;
+  const double *Sc = S + s_class_off[dp];
+  const int total = d << d;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int k = idx >> d;
+    const uint32_t p = (uint32_t)(idx & ((1 << d) - 1));
+    double v = 0.0;
+    if (pn[k].first) {
+      const int64_t row = (int64_t)pn[k].merge * K;
+      v = Sc[(int64_t)g.col_l * R + row + merge_pattern(pn, d, dp, p)];
+      if (g.col_r >= 0) v += Sc[(int64_t)g.col_r * R + row + merge_pattern(pn, d, dp, p ^ 1u)];
+    }
+    tab[g.tab_off + idx] = (float)v;
+    if (tab64) tab64[g.tab_off + idx] = v;
+  }
+}
+
+// Base value: sum over groups of w_l * c[all ones] + w_r * c[all ones ^ 1],
+// times scale; one block, fixed reduction order (deterministic).
+__global__ __launch_bounds__(256) void k_base(const Group *__restrict__ groups, int64_t n_groups,
+                                              const uint32_t *__restrict__ hist,
+                                              const double *__restrict__ freq, double scale,
+                                              double *__restrict__ out) {
+  __shared__ double part[256];
+  double s = 0.0;
+  for (int64_t gi = threadIdx.x; gi < n_groups; gi += 256) {
+    const Group g = groups[gi];
+    const uint32_t all = (1u << g.depth) - 1u;
+    const double cl = hist ? (double)hist[g.hist_off + all] : freq[g.hist_off + all];
+    s += (double)g.w_l * cl;
+    if (g.col_r >= 0) {
+      const double cr = hist ? (double)hist[g.hist_off + (all ^ 1u)] : freq[g.hist_off + (all ^ 1u)];
+      s += (double)g.w_r * cr;
+    }
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0] * scale;
+}
+
+// Section 8: freq[p] = prod over path positions of r (bit 1) or 1 - r (bit 0),
+// r = cover(next node on the path) / cover(node); one block per group.
+__global__ __launch_bounds__(256) void k_pd_freq(const Group *__restrict__ groups,
+                                                 const double *__restrict__ ratio, double *__restrict__ freq) {
+  const Group g = groups[blockIdx.x];
+  const int d = g.depth;
+  const double *r = ratio + g.path_off;
+  for (uint32_t p = threadIdx.x; p < (1u << d); p += blockDim.x) {
+    double v = 1.0;
+    for (int k = 0; k < d; ++k) v *= ((p >> (d - 1 - k)) & 1u) ? r[k] : 1.0 - r[k];
+    freq[g.hist_off + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_hist_generic(const Group *groups, const PathNode *path, int64_t n_groups, const float *B,
+                               int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s) {
+  if (m <= 0 || n_groups <= 0) return hipSuccess;
+  dim3 grid((unsigned)((m + 255) / 256), (unsigned)((n_groups + kGroupsPerBlock - 1) / kGroupsPerBlock));
+  hipLaunchKernelGGL(k_hist_generic, grid, dim3(256), 0, s, groups, path, n_groups, B, m, ldb, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_explain_generic(const Group *groups, const PathNode *path, int64_t n_groups, const float *tab,
+                                  const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, int F,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_explain_generic, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, groups, path,
+                     n_groups, tab, X, n, ldx, phi, ldphi, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_patterns(const Group *groups, const PathNode *path, int64_t n_groups, const float *X,
+                           int64_t n, int64_t ldx, uint32_t *out, hipStream_t s) {
+  if (n <= 0 || n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_patterns, dim3((unsigned)((n + 255) / 256), (unsigned)n_groups), dim3(256), 0, s, groups,
+                     path, n_groups, X, n, ldx, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_groups, const uint32_t *hist,
+                          const double *freq, double scale, const int64_t *class_off, double *H, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_columns, dim3((unsigned)n_groups), dim3(256), 0, s, groups, path, hist, freq, scale,
+                     class_off, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s) {
+  if (ncols <= 0 || R <= 0) return hipSuccess;
+  const int waves = ((R + 15) / 16) * ((ncols + 15) / 16);
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, M, H, S, R, K, ncols);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *s_class_off,
+                         const double *S, float *tab, double *tab64, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)n_groups), dim3(256), 0, s, groups, path, s_class_off, S, tab,
+                     tab64);
+  return hipGetLastError();
+}
+
+hipError_t launch_base(const Group *groups, int64_t n_groups, const uint32_t *hist, const double *freq,
+                       double scale, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_base, dim3(1), dim3(256), 0, s, groups, n_groups, hist, freq, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, double *freq, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pd_freq, dim3((unsigned)n_groups), dim3(256), 0, s, groups, ratio, freq);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Threshold ranks for the model-specialised kernels
+// ---------------------------------------------------------------------------
+
+// codes[w * ldc + r]: ranks of the features packed in word w of row r.  The
+// rank of x among the sorted distinct thresholds T_f of its feature is
+// #{t in T_f : t <= x}, so that x < T_f[j] exactly when rank <= j.  A NaN gets
+// the code with only the top bit set (0x80 / 0x8000): it compares below every
+// rank as a signed number and above every rank as an unsigned one, which the
+// kernels use to send it to the node's default side.
+__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t n, int64_t ldx, int F,
+                                                  const float *__restrict__ thr, const int32_t *__restrict__ thr_off,
+                                                  int wide, uint32_t *codes, int64_t ldc) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const int w = blockIdx.y;
+  const int per = wide ? 2 : 4, bits = wide ? 16 : 8;
+  uint32_t word = 0;
+  for (int s = 0; s < per; ++s) {
+    const int f = w * per + s;
+    if (f >= F) break;
+    const float x = X[(int64_t)f * ldx + r];
+    uint32_t code;
+    if (x != x) {
+      code = 1u << (bits - 1);
+    } else {
+      int lo = thr_off[f], hi = thr_off[f + 1];
+      const int base = lo;
+      while (lo < hi) {  // first index with thr > x
+        const int mid = (lo + hi) >> 1;
+        if (thr[mid] <= x) lo = mid + 1;
+        else hi = mid;
+      }
+      code = (uint32_t)(lo - base);
+    }
+    word |= code << (s * bits);
+  }
+  codes[(int64_t)w * ldc + r] = word;
+}
+
+hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr, const int32_t *thr_off,
+                           int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 255) / 256), (unsigned)words), dim3(256), 0, s, X, n, ldx, F,
+                     thr, thr_off, wide, codes, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace wdf

@@ -1,0 +1,367 @@
+"""Python binding of the C ABI in include/wdf.h (ctypes; argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels.  PyTorch
+provides device memory and streams: matrices are torch CUDA tensors of shape
+[n_features, n] (column-major per row: element (feature f, row r) is X[f, r])
+and calls enqueue on torch's current stream unless another is given.
+The library must be built (``python -m paper_2511_09376_amd.build``); loading
+fails loudly when it is not.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import sys
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwdf.so")
+
+OK = 0
+E_INVALID_ARG = -1
+E_UNSUPPORTED = -2
+E_OOM = -3
+E_DEVICE = -4
+E_BUSY = -5
+E_TIMEOUT = -6
+E_COMPILE = -7
+
+SHAPLEY = 0
+BANZHAF = 1
+
+KERNEL_AUTO = 0
+KERNEL_GENERIC = 1
+KERNEL_SPECIALISED = 2
+
+MAX_DEPTH = 8
+
+
+class WdfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"wdf error {code}: {msg}")
+        self.code = code
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [
+        ("n_trees", C.c_int32), ("n_features", C.c_int32),
+        ("node_offset", C.c_void_p), ("feature", C.c_void_p), ("left", C.c_void_p),
+        ("right", C.c_void_p), ("threshold", C.c_void_p), ("value", C.c_void_p),
+        ("default_left", C.c_void_p), ("cover", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+        ("batches", C.c_uint64), ("rows", C.c_uint64),
+        ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+        ("busy_ms", C.c_double),
+    ]
+
+
+_lib = None
+_live = []   # weak references to open handles, in creation order
+
+
+def _track(obj):
+    _live.append(weakref.ref(obj))
+
+
+@atexit.register
+def _close_all():
+    """Release handles newest first while the HIP runtime is still up."""
+    for ref in reversed(_live):
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _live.clear()
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
+
+EXPORTS = [
+    "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
+    "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
+    "wdf_base_value", "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
+    "wdf_debug_specialised_source", "wdf_server_create",
+    "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
+]
+
+
+def lib():
+    """Load libwdf.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_09376_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32, I = C.c_void_p, C.c_int64, C.c_int32, C.c_int
+        L.wdf_last_error.restype = C.c_char_p
+        L.wdf_create.argtypes = [I, C.POINTER(P)]
+        L.wdf_destroy.argtypes = [P]
+        L.wdf_model_load.argtypes = [P, P, I, C.POINTER(P)]
+        L.wdf_model_destroy.argtypes = [P]
+        L.wdf_model_groups.argtypes = [P, P, P, P, P, P, P]
+        L.wdf_model_groups.restype = I64
+        L.wdf_model_specialised.argtypes = [P]
+        L.wdf_background_load.argtypes = [P, P, I64, I64, I, I, P, C.POINTER(P)]
+        L.wdf_pathdep_load.argtypes = [P, I, P, C.POINTER(P)]
+        L.wdf_bg_destroy.argtypes = [P]
+        L.wdf_explain.argtypes = [P, P, I64, I64, P, I64, P]
+        L.wdf_base_value.argtypes = [P, C.POINTER(C.c_double)]
+        L.wdf_debug_patterns.argtypes = [P, P, I64, I64, P, P]
+        L.wdf_debug_histograms.argtypes = [P, P, I64]
+        L.wdf_debug_histograms.restype = I64
+        L.wdf_debug_tables.argtypes = [P, P, I64]
+        L.wdf_debug_tables.restype = I64
+        L.wdf_debug_specialised_source.argtypes = [P, I, P, I64]
+        L.wdf_debug_specialised_source.restype = I64
+        L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, C.POINTER(P)]
+        L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
+        L.wdf_server_wait.argtypes = [P, C.c_uint64, I]
+        L.wdf_server_stats.argtypes = [P, C.POINTER(Stats)]
+        L.wdf_server_destroy.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise WdfError(rc, lib().wdf_last_error().decode())
+    return rc
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _colmajor_tensor(X, F, what):
+    import torch
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor of shape [n_features, n]")
+    if X.dtype != torch.float32 or X.dim() != 2 or X.shape[0] != F or (X.shape[1] > 1 and X.stride(1) != 1):
+        raise ValueError(f"{what}: need float32 [{F}, n] with unit stride along rows, got {tuple(X.shape)} "
+                         f"{X.dtype} strides {X.stride()}")
+    return X
+
+
+def _model_desc(ens, with_cover=True):
+    keep = [np.ascontiguousarray(ens.node_offset, np.int64), np.ascontiguousarray(ens.feature, np.int32),
+            np.ascontiguousarray(ens.left, np.int32), np.ascontiguousarray(ens.right, np.int32),
+            np.ascontiguousarray(ens.threshold, np.float32), np.ascontiguousarray(ens.value, np.float32),
+            np.ascontiguousarray(ens.default_left, np.uint8)]
+    cover = getattr(ens, "cover", None)
+    cov = np.ascontiguousarray(cover, np.float64) if (with_cover and cover is not None) else None
+    if cov is not None:
+        keep.append(cov)
+    desc = _ModelDesc(int(ens.node_offset.shape[0] - 1), int(ens.n_features), *[a.ctypes.data for a in keep[:7]],
+                      cov.ctypes.data if cov is not None else None)
+    return desc, keep
+
+
+def specialised_source(ens, compile: bool = False) -> str:
+    """Generated source of the model-specialised kernels (no GPU needed);
+    with compile=True also compiles it for gfx950 with hipRTC."""
+    desc, keep = _model_desc(ens)
+    n = _check(lib().wdf_debug_specialised_source(C.byref(desc), int(compile), None, 0))
+    buf = C.create_string_buffer(n + 1)
+    _check(lib().wdf_debug_specialised_source(C.byref(desc), 0, buf, n + 1))
+    return buf.value.decode()
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().wdf_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+        _track(self)
+
+    def close(self):
+        if self.h:
+            lib().wdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """An ensemble (synth.Ensemble-like object) resident on the context's device."""
+
+    def __init__(self, ctx: Context, ens, kernel: int = KERNEL_AUTO, with_cover: bool = True):
+        self.ctx = ctx
+        self.n_features = int(ens.n_features)
+        desc, keep = _model_desc(ens, with_cover)
+        h = C.c_void_p()
+        _check(lib().wdf_model_load(ctx.h, C.byref(desc), kernel, C.byref(h)))
+        self.h = h
+        _track(self)
+
+    @property
+    def specialised(self) -> bool:
+        return bool(lib().wdf_model_specialised(self.h))
+
+    def groups(self) -> dict:
+        G = _check(lib().wdf_model_groups(self.h, None, None, None, None, None, None))
+        a = dict(tree=np.empty(G, np.int32), depth=np.empty(G, np.int32), leaf_left=np.empty(G, np.int64),
+                 leaf_right=np.empty(G, np.int64), hist_offset=np.empty(G, np.int64),
+                 table_offset=np.empty(G, np.int64))
+        _check(lib().wdf_model_groups(self.h, *[x.ctypes.data for x in a.values()]))
+        return a
+
+    def patterns(self, X, stream=None):
+        """uint32 patterns [n_groups][n] as a torch CUDA tensor (debug / parity)."""
+        import torch
+        X = _colmajor_tensor(X, self.n_features, "X")
+        n = X.shape[1]
+        G = _check(lib().wdf_model_groups(self.h, None, None, None, None, None, None))
+        out = torch.empty((G, n), dtype=torch.int32, device=X.device)
+        _check(lib().wdf_debug_patterns(self.h, C.c_void_p(X.data_ptr()), n, X.stride(0) if n else 0,
+                                        C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wdf_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Background:
+    """A background summary (histograms + tables) for one value kind."""
+
+    def __init__(self, model: Model, B=None, values: int = SHAPLEY, stream=None, pathdep: bool = False):
+        self.model = model
+        h = C.c_void_p()
+        if pathdep:
+            _check(lib().wdf_pathdep_load(model.h, values, _stream_handle(stream), C.byref(h)))
+            self.m = 0
+        else:
+            import torch
+            if isinstance(B, torch.Tensor):
+                B = _colmajor_tensor(B, model.n_features, "B")
+                m = B.shape[1]
+                _check(lib().wdf_background_load(model.h, C.c_void_p(B.data_ptr()), m, B.stride(0), 1, values,
+                                                 _stream_handle(stream), C.byref(h)))
+            else:
+                Bn = np.ascontiguousarray(B, np.float32)
+                if Bn.ndim != 2 or Bn.shape[0] != model.n_features:
+                    raise ValueError("B must be [n_features, m]")
+                m = Bn.shape[1]
+                _check(lib().wdf_background_load(model.h, Bn.ctypes.data_as(C.c_void_p), m, m, 0, values,
+                                                 _stream_handle(stream), C.byref(h)))
+            self.m = m
+        self.h = h
+        _track(self)
+
+    @property
+    def base_value(self) -> float:
+        v = C.c_double()
+        _check(lib().wdf_base_value(self.h, C.byref(v)))
+        return v.value
+
+    def explain(self, X, out=None, stream=None):
+        """phi [n_features, n] float32 CUDA tensor for consumer rows X [n_features, n]."""
+        import torch
+        F = self.model.n_features
+        X = _colmajor_tensor(X, F, "X")
+        n = X.shape[1]
+        if out is None:
+            out = torch.empty((F, n), dtype=torch.float32, device=X.device)
+        else:
+            out = _colmajor_tensor(out, F, "out")
+        ldx = X.stride(0) if n else 0
+        ldp = out.stride(0) if n else 0
+        _check(lib().wdf_explain(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldp,
+                                 _stream_handle(stream)))
+        return out
+
+    def histograms(self) -> np.ndarray:
+        n = _check(lib().wdf_debug_histograms(self.h, None, 0))
+        out = np.empty(n, np.uint32)
+        _check(lib().wdf_debug_histograms(self.h, out.ctypes.data_as(C.c_void_p), n))
+        return out
+
+    def tables(self) -> np.ndarray:
+        n = _check(lib().wdf_debug_tables(self.h, None, 0))
+        out = np.empty(n, np.float32)
+        _check(lib().wdf_debug_tables(self.h, out.ctypes.data_as(C.c_void_p), n))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wdf_bg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching explain server over a resident background summary."""
+
+    def __init__(self, bg: Background, mem_budget: int, max_rows: int = 4096, queue_cap: int = 1 << 16):
+        self.bg = bg
+        h = C.c_void_p()
+        _check(lib().wdf_server_create(bg.h, mem_budget, max_rows, queue_cap, C.byref(h)))
+        self.h = h
+        _track(self)
+
+    def submit(self, X: np.ndarray, phi: np.ndarray) -> int:
+        """X: float32 [F, n] host array (C order); phi: float32 [F, n] host array to fill."""
+        t = C.c_uint64()
+        n = X.shape[1]
+        _check(lib().wdf_server_submit(self.h, X.ctypes.data_as(C.c_void_p), n, X.strides[0] // 4,
+                                       phi.ctypes.data_as(C.c_void_p), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> int:
+        return _check(lib().wdf_server_wait(self.h, ticket, timeout_ms))
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(lib().wdf_server_stats(self.h, C.byref(s)))
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wdf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,43 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wdf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wdf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["wdf_create", "wdf_model_load", "wdf_background_load", "wdf_explain", "wdf_base_value",
+              "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables", "wdf_server_create",
+              "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2511_09376_amd import wdf
+    if not os.path.exists(wdf.LIB_PATH):
+        pytest.skip("libwdf.so not built")
+    lib = ctypes.CDLL(wdf.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"missing exports: {missing}"
+    assert set(wdf.EXPORTS) <= set(declared_functions())
+    assert wdf.lib().wdf_last_error() == b""
+
+
+def test_product_path_does_not_touch_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2511_09376_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "woodelf_oracle" not in src, f
