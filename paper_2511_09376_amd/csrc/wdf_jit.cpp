@@ -236,30 +236,156 @@ std::vector<int> used_words(const wdf_model *M, const TreeIndex &ix, int64_t a, 
   return out;
 }
 
+// Background histograms by wave-wide masks.  A node's compare yields a 64-bit
+// mask of the rows (lanes) that go left.  After the compares the lanes change
+// role: lane L stands for the pattern whose bit at path position i is bit i
+// of L (positions 0..5; deeper positions are enumerated as replicas).  Its
+// accumulator is the mask of rows that follow the path with exactly its bits,
+// the AND over the path of (mask XOR E) where E = all ones when the lane's bit
+// is 0; a popcount then gives that pattern's count for the 64 rows, added to
+// the LDS histogram without conflicts (every lane owns one bin).
+struct CountGen {
+  const wdf_model *M;
+  const TreeIndex &ix;
+  std::ostringstream &o;
+  int64_t a = 0, b = 0, h0 = 0;
+  int uid = 0;
+  struct Half { std::string lo, hi; };
+  using Acc = std::vector<Half>;
+
+  std::string sel(int f) const {
+    const JitPlan &P = M->jp;
+    const int s = f % P.per_word;
+    if (P.wide) return s ? "\"WORD_1\"" : "\"WORD_0\"";
+    static const char *B[4] = {"\"BYTE_0\"", "\"BYTE_1\"", "\"BYTE_2\"", "\"BYTE_3\""};
+    return B[s];
+  }
+  bool in(int64_t g) const { return g >= a && g < b; }
+  bool sub(int64_t nd) const { return ix.gmin[(size_t)nd] < b && ix.gmax[(size_t)nd] >= a; }
+
+  void group(int64_t g, int d, const Acc &acc) {
+    const int64_t off = M->groups[(size_t)g].hist_off - h0;
+    for (size_t j = 0; j < acc.size(); ++j) {
+      const std::string c = "c" + std::to_string(uid++);
+      o << "{ u32 " << c << " = __builtin_popcount(" << acc[j].lo << ") + __builtin_popcount(" << acc[j].hi << ");";
+      if (d < 6) o << " " << c << " = lane < " << (1 << d) << "u ? " << c << " : 0u;";
+      o << " atomicAdd(&lh[" << (off + (int64_t)j) << " + adr" << d << "], " << c << "); }\n";
+    }
+  }
+
+  void node(int64_t nd, int level, const Acc &acc) {
+    if (!sub(nd)) return;
+    const int f = M->feature[(size_t)nd];
+    const int id = uid++;
+    const std::string S = "S" + std::to_string(id);
+    o << "u64 " << S << "; " << (M->default_left[(size_t)nd] ? "NDMS(" : "NDM(") << S << ", w" << f / M->jp.per_word
+      << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] << ");\n";
+    const std::string sl = "sl" + std::to_string(id), sh = "sh" + std::to_string(id);
+    o << "const u32 " << sl << " = (u32)" << S << ", " << sh << " = (u32)(" << S << " >> 32);\n";
+    const int64_t base = M->node_offset[(size_t)M->groups[(size_t)ix.gmin[(size_t)nd]].tree];
+    const int64_t L = base + M->left[(size_t)nd], R = base + M->right[(size_t)nd];
+    const bool pair = ix.pair_of[(size_t)nd] >= 0 && in(ix.pair_of[(size_t)nd]);
+    const bool need_l = pair || (ix.single_l[(size_t)nd] >= 0 && in(ix.single_l[(size_t)nd])) ||
+                        (M->feature[(size_t)L] >= 0 && sub(L));
+    const bool need_r = (ix.single_r[(size_t)nd] >= 0 && in(ix.single_r[(size_t)nd])) ||
+                        (M->feature[(size_t)R] >= 0 && sub(R));
+    Acc left, right;
+    auto var = [&](const char *tag, size_t r, int h) {
+      return std::string(tag) + std::to_string(id) + "_" + std::to_string(r) + (h ? "h" : "l");
+    };
+    if (level < 6) {
+      const std::string E = "E" + std::to_string(level);
+      const std::string xl = "xl" + std::to_string(id), xh = "xh" + std::to_string(id);
+      o << "const u32 " << xl << " = " << sl << " ^ " << E << ", " << xh << " = " << sh << " ^ " << E << ";\n";
+      for (size_t r = 0; r < acc.size(); ++r) {
+        if (need_l) {
+          left.push_back({var("L", r, 0), var("L", r, 1)});
+          o << "const u32 " << left.back().lo << " = " << acc[r].lo << " & " << xl << ", " << left.back().hi << " = "
+            << acc[r].hi << " & " << xh << ";\n";
+        }
+        if (need_r) {
+          right.push_back({var("R", r, 0), var("R", r, 1)});
+          o << "const u32 " << right.back().lo << " = " << acc[r].lo << " & ~" << xl << ", " << right.back().hi
+            << " = " << acc[r].hi << " & ~" << xh << ";\n";
+        }
+      }
+    } else {
+      // deeper positions: both values of the bit, as replicas 2r (bit 0) and 2r+1 (bit 1)
+      for (size_t r = 0; r < acc.size(); ++r) {
+        const Half one{var("A", r, 0), var("A", r, 1)}, zer{var("Z", r, 0), var("Z", r, 1)};
+        o << "const u32 " << one.lo << " = " << acc[r].lo << " & " << sl << ", " << one.hi << " = " << acc[r].hi
+          << " & " << sh << ";\n";
+        o << "const u32 " << zer.lo << " = " << acc[r].lo << " & ~" << sl << ", " << zer.hi << " = " << acc[r].hi
+          << " & ~" << sh << ";\n";
+        left.push_back(zer);   // left child: following means going left (split true)
+        left.push_back(one);
+        right.push_back(one);  // right child: following means split false
+        right.push_back(zer);
+      }
+    }
+    const int d = level + 1;
+    if (pair) {
+      group(ix.pair_of[(size_t)nd], d, left);
+      return;
+    }
+    if (ix.single_l[(size_t)nd] >= 0 && in(ix.single_l[(size_t)nd])) group(ix.single_l[(size_t)nd], d, left);
+    if (ix.single_r[(size_t)nd] >= 0 && in(ix.single_r[(size_t)nd])) group(ix.single_r[(size_t)nd], d, right);
+    if (M->feature[(size_t)L] >= 0) node(L, level + 1, left);
+    if (M->feature[(size_t)R] >= 0) node(R, level + 1, right);
+  }
+
+  void range(int64_t ga, int64_t gb) {
+    a = ga;
+    b = gb;
+    const int t0 = M->groups[(size_t)ga].tree, t1 = M->groups[(size_t)gb - 1].tree;
+    for (int t = t0; t <= t1; ++t) {
+      const int64_t root = M->node_offset[(size_t)t];
+      if (M->feature[(size_t)root] < 0) continue;
+      // `live` is always 1; the branch only splits the code into one basic
+      // block per tree, which keeps instruction selection time linear
+      o << "if (live) {\n";
+      node(root, 0, Acc{{"vl", "vh"}});
+      o << "}\n";
+    }
+  }
+};
+
 std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
   const JitPlan &P = M->jp;
-  Gen gen{M, ix};
-  std::ostringstream &o = gen.o;
+  std::ostringstream o;
+  CountGen gen{M, ix, o};
+  int maxd = 0;
+  for (const Group &g : M->groups) maxd = std::max(maxd, g.depth);
   o << kPreamble;
+  o << "typedef unsigned long long u64;\n"
+    << "#define NDM(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n"
+    << "#define NDMS(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n";
   o << "extern \"C\" __global__ __launch_bounds__(" << P.nt_hist
-    << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 rows_per_block, u32* __restrict__ hist, int live) {\n"
+    << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 tiles_per_block, u32* __restrict__ hist, int live) {\n"
     << "  __shared__ u32 lh[" << P.hist_cap << "];\n"
-    << "  const i64 r0 = (i64)blockIdx.x * rows_per_block;\n"
-    << "  i64 r1 = r0 + rows_per_block; if (r1 > m) r1 = m;\n"
-    << "  const u32 zero = 0u;\n"
-    << "  switch (blockIdx.y) {\n";
+    << "  const u32 lane = threadIdx.x & 63u;\n"
+    << "  const i64 ntiles = (m + 63) >> 6;\n"
+    << "  const i64 tb0 = (i64)blockIdx.x * tiles_per_block;\n"
+    << "  i64 tb1 = tb0 + tiles_per_block; if (tb1 > ntiles) tb1 = ntiles;\n"
+    << "  const u32 rev6 = __builtin_bitreverse32(lane) >> 26;\n";
+  for (int l = 0; l < 6; ++l) o << "  const u32 E" << l << " = (lane >> " << l << ") & 1u ? 0u : ~0u;\n";
+  for (int d = 1; d <= std::max(1, maxd); ++d)
+    o << "  const u32 adr" << d << " = " << (d <= 6 ? "rev6 >> " + std::to_string(6 - d) : "rev6 << " + std::to_string(d - 6)) << ";\n";
+  o << "  switch (blockIdx.y) {\n";
   for (size_t c = 0; c < P.hist_chunks.size(); ++c) {
     const int64_t a = P.hist_chunks[c].first, b = P.hist_chunks[c].second;
     const int64_t h0 = M->groups[(size_t)a].hist_off;
     const int64_t h1 = M->groups[(size_t)b - 1].hist_off + ((int64_t)1 << M->groups[(size_t)b - 1].depth);
+    gen.h0 = h0;
     o << "  case " << c << ": {\n"
       << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist << ") lh[i] = 0u;\n"
       << "    __syncthreads();\n"
-      << "    for (i64 row = r0 + threadIdx.x; row < r1; row += " << P.nt_hist << ") {\n";
-    for (int w : used_words(M, ix, a, b)) o << "      const u32 w" << w << " = codes[" << w << " * ldc + row];\n";
-    gen.on_group = [&](int64_t g, const std::string &p) {
-      o << "atomicAdd(&lh[" << (M->groups[(size_t)g].hist_off - h0) << " + " << p << "], 1u);\n";
-    };
+      << "    for (i64 t = tb0 + (threadIdx.x >> 6); t < tb1; t += " << P.nt_hist / 64 << ") {\n"
+      << "      const i64 row = t * 64 + lane;\n"
+      << "      const i64 rr = row < m ? row : m - 1;\n"
+      << "      const u64 V = __ballot(row < m);\n"
+      << "      const u32 vl = (u32)V, vh = (u32)(V >> 32);\n";
+    for (int w : used_words(M, ix, a, b)) o << "      const u32 w" << w << " = codes[" << w << " * ldc + rr];\n";
     gen.range(a, b);
     o << "    }\n"
       << "    __syncthreads();\n"
@@ -456,14 +582,15 @@ int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *his
                                  P.words, codes.as<uint32_t>(), m, s);
   if (e != hipSuccess) return hip_error(e, "quantize");
   const int chunks = (int)P.hist_chunks.size();
+  const int64_t ntiles = (m + 63) / 64;
   int64_t blocks = std::max<int64_t>(1, (2 * (int64_t)M->ctx->n_cu + chunks - 1) / chunks);
-  blocks = std::min<int64_t>(blocks, (m + P.nt_hist - 1) / P.nt_hist);
-  int64_t rows_per_block = (m + blocks - 1) / blocks;
-  blocks = (m + rows_per_block - 1) / rows_per_block;
+  blocks = std::min<int64_t>(blocks, (ntiles + P.nt_hist / 64 - 1) / (P.nt_hist / 64));
+  int64_t tiles_per_block = (ntiles + blocks - 1) / blocks;
+  blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
   const uint32_t *cp = codes.as<uint32_t>();
   int64_t ldc = m;
   int live = 1;
-  void *args[] = {(void *)&cp, &ldc, &m, &rows_per_block, &hist, &live};
+  void *args[] = {(void *)&cp, &ldc, &m, &tiles_per_block, &hist, &live};
   e = hipModuleLaunchKernel(M->jit->hist, (unsigned)blocks, (unsigned)chunks, 1, (unsigned)P.nt_hist, 1, 1, 0, s, args,
                             nullptr);
   if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(hist)");

@@ -298,41 +298,52 @@ hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *r
 // the code with only the top bit set (0x80 / 0x8000): it compares below every
 // rank as a signed number and above every rank as an unsigned one, which the
 // kernels use to send it to the node's default side.
+// One block: one word, kQuantRows rows.  The word's thresholds are staged in
+// LDS when they fit; the search takes the same number of steps in every lane.
+constexpr int kQuantRows = 2048;
+constexpr int kQuantLds = 4096;
+
 __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t n, int64_t ldx, int F,
                                                   const float *__restrict__ thr, const int32_t *__restrict__ thr_off,
                                                   int wide, uint32_t *codes, int64_t ldc) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
+  __shared__ float st[kQuantLds];
   const int w = blockIdx.y;
   const int per = wide ? 2 : 4, bits = wide ? 16 : 8;
-  uint32_t word = 0;
-  for (int s = 0; s < per; ++s) {
-    const int f = w * per + s;
-    if (f >= F) break;
-    const float x = X[(int64_t)f * ldx + r];
-    uint32_t code;
-    if (x != x) {
-      code = 1u << (bits - 1);
-    } else {
-      int lo = thr_off[f], hi = thr_off[f + 1];
-      const int base = lo;
-      while (lo < hi) {  // first index with thr > x
-        const int mid = (lo + hi) >> 1;
-        if (thr[mid] <= x) lo = mid + 1;
-        else hi = mid;
+  const int f0 = w * per, f1 = min(F, f0 + per);
+  const int lo = thr_off[f0], hi = thr_off[f1];
+  const bool staged = hi - lo <= kQuantLds;
+  if (staged)
+    for (int i = threadIdx.x; i < hi - lo; i += 256) st[i] = thr[lo + i];
+  __syncthreads();
+  // thresholds of this word's features, indexed from the first one (both
+  // pointers stay inside their arrays)
+  const float *T = staged ? st : thr + lo;
+  const int64_t r0 = (int64_t)blockIdx.x * kQuantRows;
+  for (int64_t r = r0 + threadIdx.x; r < r0 + kQuantRows && r < n; r += 256) {
+    uint32_t word = 0;
+    for (int f = f0; f < f1; ++f) {
+      const float x = X[(int64_t)f * ldx + r];
+      const int b = thr_off[f] - lo, K = thr_off[f + 1] - thr_off[f];
+      uint32_t code;
+      if (x != x) {
+        code = 1u << (bits - 1);
+      } else {
+        int pos = 0;  // thresholds known to be <= x
+        for (int step = K ? (1 << (31 - __builtin_clz((unsigned)K))) : 0; step > 0; step >>= 1)
+          if (pos + step <= K && T[b + pos + step - 1] <= x) pos += step;
+        code = (uint32_t)pos;
       }
-      code = (uint32_t)(lo - base);
+      word |= code << ((f - f0) * bits);
     }
-    word |= code << (s * bits);
+    codes[(int64_t)w * ldc + r] = word;
   }
-  codes[(int64_t)w * ldc + r] = word;
 }
 
 hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr, const int32_t *thr_off,
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + 255) / 256), (unsigned)words), dim3(256), 0, s, X, n, ldx, F,
-                     thr, thr_off, wide, codes, ldc);
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + kQuantRows - 1) / kQuantRows), (unsigned)words), dim3(256), 0, s,
+                     X, n, ldx, F, thr, thr_off, wide, codes, ldc);
   return hipGetLastError();
 }
 

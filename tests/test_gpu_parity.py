@@ -43,7 +43,7 @@ def _kernel(wdf, name):
 
 def _load(wdf, ctx, ens, kname):
     """Load a model; with kname "auto" the specialised kernels must be the ones in use."""
-    model = _load(wdf, ctx, ens, kname)
+    model = wdf.Model(ctx, ens, _kernel(wdf, kname))
     assert model.specialised == (kname == "auto"), f"kernel choice {kname}: specialised={model.specialised}"
     return model
 
