@@ -83,6 +83,63 @@ def cpu_baseline(ens, X_rows, B, seconds_hint=20.0):
                       f"rate scaled by {m_s}/{m} to the full background (the oracle's work is linear in it)"}
 
 
+def serve_bench(wdf, ctx, loads=(0.5, 0.8), n_requests=10_000, max_rows=4096):
+    """Serving: the 100-tree depth-6 model and a 100k-row background resident on
+    the device; requests of log-uniform size in [1, 4096] rows arrive as a
+    Poisson process at a fixed fraction of the server's saturated throughput.
+    Continuous batching is compared with one request per launch at the same
+    offered load.  Latency is submit -> phi on the host."""
+    import torch
+    w = synth.WORKLOADS["serve"]
+    ens = w.ensemble()
+    B = w.background()
+    model = wdf.Model(ctx, ens)
+    bg = wdf.Background(model, torch.from_numpy(B).cuda())
+    s_sizes, s_arrival = w.seeds()[3].spawn(2)
+    sizes = synth.request_sizes(n_requests, s_sizes, max_rows)
+    pool = w.consumers(max_rows * 4)          # request rows are drawn from this pool
+    starts = np.random.default_rng(s_arrival).integers(0, pool.shape[1] - max_rows, n_requests)
+    reqs = [np.ascontiguousarray(pool[:, s:s + n]) for s, n in zip(starts, sizes)]
+    outs = [np.empty_like(x) for x in reqs]
+    F = model.n_features
+    budget = 4 * (4 * F * max_rows * 4)
+
+    def run(one_per_launch, rate_rows):
+        srv = wdf.Server(bg, budget, max_rows, queue_cap=n_requests, one_per_launch=one_per_launch)
+        gaps = np.random.default_rng(7).exponential(1.0, n_requests) if rate_rows else np.zeros(n_requests)
+        mean_size = float(sizes.mean())
+        if rate_rows:
+            gaps *= mean_size / rate_rows
+        t_arr = np.cumsum(gaps)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(n_requests):
+            target = t0 + t_arr[i]
+            while time.perf_counter() < target:
+                pass
+            tickets.append(srv.submit(reqs[i], outs[i]))
+        for t in tickets:
+            srv.wait(t)
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return {"rows_per_s": float(sizes.sum()) / dt, "requests": int(st.completed), "batches": int(st.batches),
+                "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "max_ms": st.max_ms}
+
+    run(False, 0)                                  # warm-up
+    cap = run(False, 0)                            # saturated throughput
+    out = {"workload": "100 complete depth-6 trees, 127 features, 100k background rows resident; "
+                       f"{n_requests} Poisson requests, sizes log-uniform in [1, {max_rows}] (mean {sizes.mean():.0f} rows)",
+           "saturated_rows_per_s": cap["rows_per_s"], "loads": []}
+    for load in loads:
+        rate = load * cap["rows_per_s"]
+        out["loads"].append({"offered_fraction": load, "offered_rows_per_s": rate,
+                             "continuous_batching": run(False, rate), "one_request_per_launch": run(True, rate)})
+    bg.close()
+    model.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +149,7 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialised"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (rows shard across GPUs "
@@ -159,6 +217,11 @@ def main():
            "roofline": roofline, "base_value": base,
            "explain_rows_per_s": n / (explain_ms * 1e-3),
            "background_ms": ms_step - explain_ms}
+    if not args.no_serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serve_bench(wdf, ctx)
+        sv = out["serving"]["loads"][0]["continuous_batching"]
+        out["served_p50_ms"], out["served_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ens, X[:, :64], B, args.cpu_seconds)

@@ -178,19 +178,28 @@ typedef struct {
   uint64_t batches;           /* device launches */
   uint64_t rows;              /* rows explained */
   double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result on host */
-  double busy_ms;             /* sum of device batch times */
+  double busy_ms;             /* sum over batches of device time from copy-in to copy-out */
 } wdf_stats;
 
-/* A server keeps bg resident, owns pinned staging slots totalling at most
- * mem_budget bytes and a worker thread that forms batches of up to max_rows
- * rows from queued requests, copies them in, runs wdf_explain and copies
- * results out, overlapping consecutive batches on two streams.  Requests of
- * 1..max_rows rows are admitted as slot memory frees up.
- * Errors: INVALID_ARG (budget too small for one batch), OOM, DEVICE. */
-int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int queue_cap, wdf_server **out);
+/* A server keeps bg resident and owns a worker thread and up to four batch
+ * slots, each with pinned host staging, device buffers for X and phi, a stream
+ * and events; the slots it creates are those that fit in mem_budget bytes
+ * (4 * n_features * max_rows * 4 bytes each).  Queued requests of 1..max_rows
+ * rows are admitted FIFO as slots free up: a batch packs the oldest requests
+ * that fit in max_rows rows (one request per batch with
+ * WDF_SERVE_ONE_PER_LAUNCH), is copied in, explained and copied out on its
+ * slot's stream, so batches of different slots overlap on the device.  Each
+ * result is bit-identical to wdf_explain on the same rows alone.  The server
+ * must be destroyed before bg.  Errors: INVALID_ARG (budget below one slot,
+ * max_rows or queue_cap < 1), OOM, DEVICE. */
+#define WDF_SERVE_ONE_PER_LAUNCH 1
+int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int queue_cap, int flags,
+                      wdf_server **out);
 /* Enqueue n rows of host X (column-major, ldx >= n); phi_host receives
- * [n_features][n] column-major float32 when the ticket completes.  X is copied
- * before return.  Errors: INVALID_ARG, BUSY (queue full). */
+ * [n_features][n] column-major float32 when the ticket completes.  Both stay
+ * owned by the caller and must remain valid until wdf_server_wait has returned
+ * for the ticket (the rows are read when the request enters a batch).
+ * Errors: INVALID_ARG (n outside 1..max_rows), BUSY (queue full). */
 int wdf_server_submit(wdf_server *srv, const float *X_host, int64_t n, int64_t ldx, float *phi_host,
                       uint64_t *ticket);
 /* Wait until the ticket completes (timeout_ms < 0: forever).  Errors: TIMEOUT,

@@ -37,6 +37,7 @@ KERNEL_GENERIC = 1
 KERNEL_SPECIALISED = 2
 
 MAX_DEPTH = 8
+SERVE_ONE_PER_LAUNCH = 1
 
 
 class WdfError(RuntimeError):
@@ -125,7 +126,7 @@ def lib():
         L.wdf_debug_tables.restype = I64
         L.wdf_debug_specialised_source.argtypes = [P, I, P, I64]
         L.wdf_debug_specialised_source.restype = I64
-        L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, C.POINTER(P)]
+        L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
         L.wdf_server_wait.argtypes = [P, C.c_uint64, I]
         L.wdf_server_stats.argtypes = [P, C.POINTER(Stats)]
@@ -330,23 +331,35 @@ class Background:
 class Server:
     """Continuous-batching explain server over a resident background summary."""
 
-    def __init__(self, bg: Background, mem_budget: int, max_rows: int = 4096, queue_cap: int = 1 << 16):
+    def __init__(self, bg: Background, mem_budget: int, max_rows: int = 4096, queue_cap: int = 1 << 16,
+                 one_per_launch: bool = False):
         self.bg = bg
+        self.n_features = bg.model.n_features
+        self._inflight = {}
         h = C.c_void_p()
-        _check(lib().wdf_server_create(bg.h, mem_budget, max_rows, queue_cap, C.byref(h)))
+        _check(lib().wdf_server_create(bg.h, mem_budget, max_rows, queue_cap, SERVE_ONE_PER_LAUNCH if one_per_launch else 0,
+                                       C.byref(h)))
         self.h = h
         _track(self)
 
     def submit(self, X: np.ndarray, phi: np.ndarray) -> int:
-        """X: float32 [F, n] host array (C order); phi: float32 [F, n] host array to fill."""
+        """X: float32 [F, n] host array (C order); phi: float32 [F, n] C-order host array that
+        receives the values; both must stay alive until wait() returns."""
+        if X.dtype != np.float32 or X.ndim != 2 or X.shape[0] != self.n_features or X.strides[1] != 4:
+            raise ValueError("X must be float32 [n_features, n] with unit stride along rows")
+        if phi.dtype != np.float32 or phi.shape != X.shape or not phi.flags.c_contiguous:
+            raise ValueError("phi must be a C-contiguous float32 array shaped like X")
         t = C.c_uint64()
         n = X.shape[1]
         _check(lib().wdf_server_submit(self.h, X.ctypes.data_as(C.c_void_p), n, X.strides[0] // 4,
                                        phi.ctypes.data_as(C.c_void_p), C.byref(t)))
+        self._inflight[t.value] = (X, phi)   # the library reads X and writes phi until wait()
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> int:
-        return _check(lib().wdf_server_wait(self.h, ticket, timeout_ms))
+        rc = _check(lib().wdf_server_wait(self.h, ticket, timeout_ms))
+        self._inflight.pop(ticket, None)
+        return rc
 
     def stats(self) -> Stats:
         s = Stats()
