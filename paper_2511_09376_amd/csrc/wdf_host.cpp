@@ -76,6 +76,11 @@ int DevBuf::alloc(size_t n) {
   return WDF_OK;
 }
 
+int ws_reserve(DevBuf &buf, size_t bytes) {
+  if (buf.bytes >= bytes && buf.ptr) return WDF_OK;
+  return buf.alloc(std::max<size_t>(bytes, 256));
+}
+
 }  // namespace wdf
 
 // Copy a host vector into a fresh device buffer.  The copy completes before
@@ -446,11 +451,11 @@ static hipStream_t pick_stream(wdf_ctx *, void *s) { return (hipStream_t)s; }
 // Columns, MFMA products per class, expansion into the gather tables, base value.
 static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
                     hipStream_t s) {
-  DevBuf H, S, base;
+  DevBuf &H = M->ws_H, &S = M->ws_S, &base = M->ws_base;
   int rc;
-  if ((rc = H.alloc((size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
-  if ((rc = S.alloc((size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
-  if ((rc = base.alloc(sizeof(double)))) return rc;
+  if ((rc = ws_reserve(H, (size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
+  if ((rc = ws_reserve(S, (size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
+  if ((rc = ws_reserve(base, sizeof(double)))) return rc;
   if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(M->tab_size, 1) * sizeof(float)))) return rc;
   const int64_t G = (int64_t)M->groups.size();
   HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));  // padding between tables
@@ -484,6 +489,7 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   hipStream_t s = pick_stream(M->ctx, hip_stream);
   std::unique_ptr<wdf_bg> bg(new (std::nothrow) wdf_bg());
   if (!bg) return set_error(WDF_E_OOM, "wdf_background_load: out of host memory");
+  std::lock_guard<std::mutex> ws_lock(M->ws_mu);
   bg->model = M;
   bg->device = M->device;
   bg->m = m;
@@ -521,6 +527,7 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   hipStream_t s = pick_stream(M->ctx, hip_stream);
   std::unique_ptr<wdf_bg> bg(new (std::nothrow) wdf_bg());
   if (!bg) return set_error(WDF_E_OOM, "wdf_pathdep_load: out of host memory");
+  std::lock_guard<std::mutex> ws_lock(M->ws_mu);
   bg->model = M;
   bg->device = M->device;
   bg->m = 0;

@@ -41,10 +41,15 @@ struct JitPlan {
   std::vector<int32_t> rank;    // per node: index of its threshold among its feature's
   int nt_hist = 512, nt_explain = 512;
   int hist_cap = 32768;         // uint32 counters per histogram chunk (LDS)
-  int stage_floats = 12288;     // table floats per explain stage (LDS, double-buffered)
+  int stage_floats_max = 12288; // table floats per explain stage (LDS, double-buffered)
+  int stage_floats = 12288;     // the same after room for the thresholds
+  std::vector<float> thr_pad;   // used features' thresholds, NaN-padded to powers of two
+  std::vector<int32_t> thr_pad_off, thr_steps;  // per feature: offset in thr_pad, search steps
   std::vector<std::pair<int64_t, int64_t>> hist_chunks;    // group ranges
   std::vector<std::pair<int64_t, int64_t>> explain_stages; // group ranges
-  DevBuf d_thr, d_thr_off;
+  std::vector<uint32_t> perm;   // histogram bin of every LDS slot (absolute offsets)
+  int hist_rounds = 2;          // histogram blocks per CU over the whole launch
+  DevBuf d_thr, d_thr_off, d_perm, d_thr_pad;
 };
 
 // Per-class contraction shape: paths with dprime distinct features.
@@ -93,6 +98,12 @@ struct wdf_model {
   // model-specialised kernels
   std::shared_ptr<wdf::JitModule> jit;
   wdf::JitPlan jp;
+
+  // workspace of background summaries (threshold codes, contraction columns
+  // and products), grown on demand and reused; ws_mu serialises summaries of
+  // one model
+  std::mutex ws_mu;
+  wdf::DevBuf ws_codes, ws_H, ws_S, ws_base;
 };
 
 struct wdf_bg {
@@ -112,5 +123,7 @@ int jit_build(wdf_model *M);
 int jit_source(wdf_model *M, bool do_compile, std::string &src);
 int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
 int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s);
+// Grow a workspace buffer to at least `bytes` (contents are not kept).
+int ws_reserve(DevBuf &buf, size_t bytes);
 int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s);
 }  // namespace wdf

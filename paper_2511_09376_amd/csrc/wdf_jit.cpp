@@ -88,18 +88,69 @@ int make_plan(wdf_model *M) {
     const float *e = P.thr.data() + P.thr_off[(size_t)f + 1];
     P.rank[(size_t)i] = (int32_t)(std::lower_bound(b, e, M->threshold[(size_t)i]) - b);
   }
-  // histogram chunks: consecutive groups whose counters fit the LDS budget
+  // histogram chunks: consecutive groups whose counters fit the LDS budget,
+  // filled to about the same size so that every chunk is about the same work
   P.hist_chunks.clear();
   const int64_t G = (int64_t)M->groups.size();
+  int64_t total = 0;
+  for (const Group &g : M->groups) total += (int64_t)1 << g.depth;
+  const int64_t n_chunks = std::max<int64_t>(1, (total + P.hist_cap - 1) / P.hist_cap);
+  const int64_t target = (total + n_chunks - 1) / n_chunks;
   for (int64_t g = 0; g < G;) {
     int64_t a = g, size = 0;
-    while (g < G && size + ((int64_t)1 << M->groups[(size_t)g].depth) <= P.hist_cap) {
+    while (g < G && size + ((int64_t)1 << M->groups[(size_t)g].depth) <= P.hist_cap &&
+           (size < target || g == a)) {
       size += (int64_t)1 << M->groups[(size_t)g].depth;
       ++g;
     }
     if (g == a) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: histogram chunk too small");
     P.hist_chunks.push_back({a, g});
   }
+  // LDS slot of every histogram bin: bin p of a group of depth d sits at
+  // slot s with lanes of a half-wave on distinct banks (see CountGen); perm
+  // maps a slot back to its bin
+  P.perm.assign((size_t)M->hist_size, 0);
+  for (const Group &g : M->groups) {
+    const int d = g.depth;
+    for (uint32_t s = 0; s < (1u << d); ++s) {
+      uint32_t p;
+      if (d < 6) {
+        p = s;
+      } else {
+        const uint32_t lo = s & 63u, j = s >> 6;
+        const uint32_t v = ((lo << 1) | (lo >> 5)) & 63u;  // undo the rotate-right of the lane part
+        p = (v << (d - 6)) | j;
+      }
+      P.perm[(size_t)(g.hist_off + s)] = (uint32_t)(g.hist_off + p);
+    }
+  }
+  // thresholds of every used feature, padded with NaN to a power of two, for
+  // the rank search inside the explain kernel (NaN never compares <= x)
+  std::vector<char> used((size_t)F, 0);
+  for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
+  P.thr_pad.clear();
+  P.thr_pad_off.assign((size_t)F, -1);
+  P.thr_steps.assign((size_t)F, 0);
+  for (int f = 0; f < F; ++f) {
+    if (!used[(size_t)f]) continue;
+    const int K = P.thr_off[(size_t)f + 1] - P.thr_off[(size_t)f];
+    int c = 0;
+    while ((1 << c) <= K) ++c;  // 2^c > K: c steps of a branch-free search
+    P.thr_pad_off[(size_t)f] = (int32_t)P.thr_pad.size();
+    P.thr_steps[(size_t)f] = c;
+    for (int i = 0; i < (1 << c); ++i)
+      P.thr_pad.push_back(i < K ? P.thr[(size_t)(P.thr_off[(size_t)f] + i)] : std::nanf(""));
+  }
+  while (P.thr_pad.size() % 4) P.thr_pad.push_back(std::nanf(""));
+  // LDS: thresholds plus two table stages within the 160 KB of a workgroup
+  const int64_t lds_floats = 160 * 1024 / 4;
+  const int64_t room = (lds_floats - (int64_t)P.thr_pad.size()) / 2 / 4 * 4;
+  P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
+  int max_table = 0;
+  for (const Group &g : M->groups) max_table = std::max(max_table, ((g.depth << g.depth) + 3) / 4 * 4);
+  if (P.stage_floats < max_table)
+    return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %zu thresholds leave too little LDS for the tables",
+                     P.thr_pad.size());
   // explain stages: consecutive groups whose tables fit one LDS buffer
   P.explain_stages.clear();
   for (int64_t g = 0; g < G;) {
@@ -263,13 +314,19 @@ struct CountGen {
   bool in(int64_t g) const { return g >= a && g < b; }
   bool sub(int64_t nd) const { return ix.gmin[(size_t)nd] < b && ix.gmax[(size_t)nd] >= a; }
 
+  // Lane L counts the pattern whose bits at positions 0..5 are L's bits 0..5
+  // (deeper positions: replica j).  Its LDS slot is the lane part reversed
+  // into pattern order and rotated right by one bit, plus 64 j, so the 32
+  // lanes of each half-wave add to 32 distinct banks; groups shorter than six
+  // positions use only their first 2^d lanes.
   void group(int64_t g, int d, const Acc &acc) {
     const int64_t off = M->groups[(size_t)g].hist_off - h0;
     for (size_t j = 0; j < acc.size(); ++j) {
       const std::string c = "c" + std::to_string(uid++);
-      o << "{ u32 " << c << " = __builtin_popcount(" << acc[j].lo << ") + __builtin_popcount(" << acc[j].hi << ");";
-      if (d < 6) o << " " << c << " = lane < " << (1 << d) << "u ? " << c << " : 0u;";
-      o << " atomicAdd(&lh[" << (off + (int64_t)j) << " + adr" << d << "], " << c << "); }\n";
+      o << "{ const u32 " << c << " = __builtin_popcount(" << acc[j].lo << ") + __builtin_popcount(" << acc[j].hi
+        << ");";
+      if (d < 6) o << " if (lane < " << (1 << d) << "u)";
+      o << " atomicAdd(&lh[" << (off + 64 * (int64_t)j) << " + adr" << std::min(d, 6) << "], " << c << "); }\n";
     }
   }
 
@@ -361,7 +418,7 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
     << "#define NDM(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n"
     << "#define NDMS(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n";
   o << "extern \"C\" __global__ __launch_bounds__(" << P.nt_hist
-    << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 tiles_per_block, u32* __restrict__ hist, int live) {\n"
+    << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 tiles_per_block, u32* __restrict__ hist, const u32* __restrict__ perm, int live) {\n"
     << "  __shared__ u32 lh[" << P.hist_cap << "];\n"
     << "  const u32 lane = threadIdx.x & 63u;\n"
     << "  const i64 ntiles = (m + 63) >> 6;\n"
@@ -369,8 +426,8 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
     << "  i64 tb1 = tb0 + tiles_per_block; if (tb1 > ntiles) tb1 = ntiles;\n"
     << "  const u32 rev6 = __builtin_bitreverse32(lane) >> 26;\n";
   for (int l = 0; l < 6; ++l) o << "  const u32 E" << l << " = (lane >> " << l << ") & 1u ? 0u : ~0u;\n";
-  for (int d = 1; d <= std::max(1, maxd); ++d)
-    o << "  const u32 adr" << d << " = " << (d <= 6 ? "rev6 >> " + std::to_string(6 - d) : "rev6 << " + std::to_string(d - 6)) << ";\n";
+  for (int d = 1; d <= std::min(5, maxd); ++d) o << "  const u32 adr" << d << " = rev6 >> " << 6 - d << ";\n";
+  o << "  const u32 adr6 = (rev6 >> 1) | ((rev6 & 1u) << 5);\n";
   o << "  switch (blockIdx.y) {\n";
   for (size_t c = 0; c < P.hist_chunks.size(); ++c) {
     const int64_t a = P.hist_chunks[c].first, b = P.hist_chunks[c].second;
@@ -390,7 +447,7 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
     o << "    }\n"
       << "    __syncthreads();\n"
       << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist
-      << ") { const u32 v = lh[i]; if (v) atomicAdd(&hist[" << h0 << " + i], v); }\n";
+      << ") { const u32 v = lh[i]; if (v) atomicAdd(&hist[perm[" << h0 << " + i]], v); }\n";
     for (int64_t g = a; g < b; ++g)
       if (M->groups[(size_t)g].depth == 0)
         o << "    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&hist[" << M->groups[(size_t)g].hist_off
@@ -409,7 +466,7 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   std::vector<char> used((size_t)F, 0);
   for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
   o << kPreamble;
-  o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n";
+  o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n";
   o << R"(
 __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float* dst, int n16) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -419,20 +476,56 @@ __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float*
                                        (__attribute__((address_space(3))) void*)(dst + 4 * c), 16, 0, 0);
   }
 }
-// codes and phi may share memory: each block reads its rows' codes before it
-// writes its rows' values, so neither pointer is restrict-qualified.
-extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const u32* codes, i64 ldc, const float* __restrict__ tab,
-                                                                  float* phi, i64 ldphi, i64 n, int live) {
+extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* __restrict__ X, i64 ldx,
+                                                                  const float* __restrict__ tab,
+                                                                  const float* __restrict__ thr,
+                                                                  float* __restrict__ phi, i64 ldphi, i64 n, int live) {
   __shared__ __attribute__((aligned(16))) float lds[2 * SF];
+  __shared__ __attribute__((aligned(16))) float lthr[TF];
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
   const u32 zero = 0u;
+  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];
+  __syncthreads();
 )";
-  for (int w = 0; w < P.words; ++w) {
-    bool any = false;
-    for (int s = 0; s < P.per_word; ++s)
-      if (w * P.per_word + s < F && used[(size_t)(w * P.per_word + s)]) any = true;
-    if (any) o << "  const u32 w" << w << " = codes[" << w << " * ldc + rr];\n";
+  for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
+  // threshold ranks of the row, packed as the pattern kernels expect.  The
+  // searches run step-major over batches of 16 features so that 16
+  // independent LDS reads are in flight at every step.
+  const int bits = P.wide ? 16 : 8;
+  std::vector<int> uf;
+  for (int f = 0; f < F; ++f)
+    if (used[(size_t)f]) uf.push_back(f);
+  std::vector<char> word_open((size_t)P.words, 0);
+  for (size_t b0 = 0; b0 < uf.size(); b0 += 16) {
+    const size_t b1 = std::min(uf.size(), b0 + 16);
+    o << "  if (live) {\n";  // one basic block per batch: its loads are not hoisted into the previous one
+    int cmax = 0;
+    for (size_t i = b0; i < b1; ++i) {
+      const int f = uf[i];
+      o << "  const float x" << f << " = X[(i64)" << f << " * ldx + rr]; u32 r" << f << " = 0u;\n";
+      cmax = std::max(cmax, P.thr_steps[(size_t)f]);
+    }
+    for (int k = cmax - 1; k >= 0; --k) {
+      o << " ";
+      for (size_t i = b0; i < b1; ++i) {
+        const int f = uf[i];
+        if (P.thr_steps[(size_t)f] <= k) continue;
+        o << " r" << f << " += (lthr[" << P.thr_pad_off[(size_t)f] + (1 << k) - 1 << " + r" << f << "] <= x" << f
+          << ") ? " << (1u << k) << "u : 0u;";
+      }
+      o << "\n";
+    }
+    for (size_t i = b0; i < b1; ++i) {
+      const int f = uf[i], w = f / P.per_word, sft = (f % P.per_word) * bits;
+      if (!word_open[(size_t)w]) {
+        word_open[(size_t)w] = 1;
+        o << "  w" << w << " = 0u;\n";
+      }
+      o << "  w" << w << " |= (x" << f << " != x" << f << " ? " << (1u << (bits - 1)) << "u : r" << f << ") << " << sft
+        << ";\n";
+    }
+    o << "  }\n";
   }
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
@@ -568,6 +661,14 @@ int jit_build(wdf_model *M) {
   if ((e = hipMemcpyAsync(P.d_thr_off.ptr, P.thr_off.data(), P.thr_off.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           s)) != hipSuccess)
     return hip_error(e, "hipMemcpyAsync(threshold offsets)");
+  if ((rc = P.d_thr_pad.alloc(std::max<size_t>(P.thr_pad.size(), 1) * sizeof(float)))) return rc;
+  if (!P.thr_pad.empty() && (e = hipMemcpyAsync(P.d_thr_pad.ptr, P.thr_pad.data(), P.thr_pad.size() * sizeof(float),
+                                                hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(padded thresholds)");
+  if ((rc = P.d_perm.alloc(std::max<size_t>(P.perm.size(), 1) * sizeof(uint32_t)))) return rc;
+  if (!P.perm.empty() && (e = hipMemcpyAsync(P.d_perm.ptr, P.perm.data(), P.perm.size() * sizeof(uint32_t),
+                                             hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(perm)");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   M->jit = mod;
   return WDF_OK;
@@ -575,43 +676,40 @@ int jit_build(wdf_model *M) {
 
 int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s) {
   const JitPlan &P = M->jp;
-  DevBuf codes;
+  DevBuf &codes = M->ws_codes;  // the caller holds the model's workspace lock
   int rc;
-  if ((rc = codes.alloc((size_t)P.words * (size_t)m * sizeof(uint32_t)))) return rc;
+  if ((rc = ws_reserve(codes, (size_t)P.words * (size_t)m * sizeof(uint32_t)))) return rc;
   hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr.as<float>(), P.d_thr_off.as<int32_t>(), P.wide,
                                  P.words, codes.as<uint32_t>(), m, s);
   if (e != hipSuccess) return hip_error(e, "quantize");
+  // one block per CU at a time (the LDS histogram); a whole number of rounds
+  // over the CUs, split evenly between the chunks
   const int chunks = (int)P.hist_chunks.size();
   const int64_t ntiles = (m + 63) / 64;
-  int64_t blocks = std::max<int64_t>(1, (2 * (int64_t)M->ctx->n_cu + chunks - 1) / chunks);
+  int64_t blocks = std::max<int64_t>(1, (int64_t)P.hist_rounds * M->ctx->n_cu / chunks);
   blocks = std::min<int64_t>(blocks, (ntiles + P.nt_hist / 64 - 1) / (P.nt_hist / 64));
   int64_t tiles_per_block = (ntiles + blocks - 1) / blocks;
   blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
   const uint32_t *cp = codes.as<uint32_t>();
+  const uint32_t *perm = P.d_perm.as<uint32_t>();
   int64_t ldc = m;
   int live = 1;
-  void *args[] = {(void *)&cp, &ldc, &m, &tiles_per_block, &hist, &live};
+  void *args[] = {(void *)&cp, &ldc, &m, &tiles_per_block, &hist, (void *)&perm, &live};
   e = hipModuleLaunchKernel(M->jit->hist, (unsigned)blocks, (unsigned)chunks, 1, (unsigned)P.nt_hist, 1, 1, 0, s, args,
                             nullptr);
   if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(hist)");
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hist");
   return WDF_OK;
 }
 
 int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s) {
   const wdf_model *M = bg->model;
   const JitPlan &P = M->jp;
-  // threshold ranks go into the first rows of phi; the explain kernel reads a
-  // block's ranks before it writes that block's values
-  hipError_t e = launch_quantize(X, n, ldx, M->n_features, P.d_thr.as<float>(), P.d_thr_off.as<int32_t>(), P.wide,
-                                 P.words, reinterpret_cast<uint32_t *>(phi), ldphi, s);
-  if (e != hipSuccess) return hip_error(e, "quantize");
-  const uint32_t *cp = reinterpret_cast<const uint32_t *>(phi);
   const float *tab = bg->d_tab.as<float>();
+  const float *thr = P.d_thr_pad.as<float>();
   int live = 1;
-  void *args[] = {(void *)&cp, &ldphi, (void *)&tab, &phi, &ldphi, &n, &live};
+  void *args[] = {(void *)&X, &ldx, (void *)&tab, (void *)&thr, &phi, &ldphi, &n, &live};
   const unsigned blocks = (unsigned)((n + P.nt_explain - 1) / P.nt_explain);
-  e = hipModuleLaunchKernel(M->jit->explain, blocks, 1, 1, (unsigned)P.nt_explain, 1, 1, 0, s, args, nullptr);
+  hipError_t e = hipModuleLaunchKernel(M->jit->explain, blocks, 1, 1, (unsigned)P.nt_explain, 1, 1, 0, s, args, nullptr);
   if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(explain)");
   return WDF_OK;
 }
