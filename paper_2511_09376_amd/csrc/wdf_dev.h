@@ -28,4 +28,21 @@ struct Group {
   float w_l, w_r;     // leaf values (w_r = 0 for a single)
 };
 
+// A unit of the explain tables: a group's table, or a "quad": the two pair
+// groups below the children of one node, merged into one table indexed by
+// (path prefix, split at the node, split at its left child, split at its right
+// child) with d + 1 values per entry (d = the pairs' depth).  Explain tables
+// are indexed by raw splits (bit 1: the row went left), not by whether the row
+// follows the path; `mask` holds the path's right turns, so the pattern of a
+// raw index r is r ^ mask.
+struct XUnit {
+  int64_t src_l;   // table offset of the (left) group
+  int64_t src_r;   // table offset of the right pair group of a quad, -1 otherwise
+  int64_t dst;     // offset in the explain tables
+  int32_t depth;   // depth of the group(s)
+  int32_t quad;    // 1 for a quad
+  uint32_t mask;   // right turns: all d positions of a group, the d - 2 prefix positions of a quad
+  uint32_t pad_;
+};
+
 }  // namespace wdf

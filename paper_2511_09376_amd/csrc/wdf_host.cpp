@@ -391,6 +391,8 @@ static int upload_model(wdf_model *M) {
 extern "C" int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out) {
   if (!ctx || !desc || !out) return set_error(WDF_E_INVALID_ARG, "wdf_model_load: NULL argument");
   *out = nullptr;
+  const bool quads = (kernel & WDF_KERNEL_QUADS) != 0;
+  kernel &= ~WDF_KERNEL_QUADS;
   if (kernel < WDF_KERNEL_AUTO || kernel > WDF_KERNEL_SPECIALISED)
     return set_error(WDF_E_INVALID_ARG, "wdf_model_load: unknown kernel choice %d", kernel);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -406,6 +408,7 @@ extern "C" int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kern
   }
   if ((rc = upload_model(M.get()))) return rc;
   if (kernel != WDF_KERNEL_GENERIC) {
+    M->jp.quads = quads;
     rc = jit_build(M.get());
     if (rc != WDF_OK) {
       if (kernel == WDF_KERNEL_SPECIALISED) return rc;
@@ -470,6 +473,12 @@ static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double
   }
   HIP_TRY(launch_expand(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_sclass_off.as<int64_t>(),
                         S.as<double>(), bg->d_tab.as<float>(), nullptr, s));
+  if (M->jit) {  // explain tables of the specialised kernel: quads merged from pairs
+    if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->jp.xtab_size, 1) * sizeof(float)))) return rc;
+    HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
+    HIP_TRY(launch_xtab(M->jp.d_xunits.as<XUnit>(), (int64_t)M->jp.xunits.size(), bg->d_tab.as<float>(),
+                        bg->d_xtab.as<float>(), s));
+  }
   HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0,
                       base.as<double>(), s));
   HIP_TRY(hipMemcpyAsync(&bg->base, base.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -613,12 +622,14 @@ extern "C" int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t c
   return n;
 }
 
-extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int do_compile, char *out, int64_t cap) {
+extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int do_compile, char *out,
+                                                int64_t cap) {
   if (!desc) return set_error(WDF_E_INVALID_ARG, "wdf_debug_specialised_source: NULL desc");
   try {
     wdf_model M;
     int rc = validate_and_layout(desc, &M);
     if (rc) return rc;
+    M.jp.quads = (kernel & WDF_KERNEL_QUADS) != 0;
     std::string src;
     if ((rc = jit_source(&M, do_compile != 0, src))) return rc;
     if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);

@@ -48,8 +48,13 @@ struct JitPlan {
   std::vector<std::pair<int64_t, int64_t>> hist_chunks;    // group ranges
   std::vector<std::pair<int64_t, int64_t>> explain_stages; // group ranges
   std::vector<uint32_t> perm;   // histogram bin of every LDS slot (absolute offsets)
+  std::vector<XUnit> xunits;    // explain-table units in group order
+  std::vector<int64_t> unit_g0; // first group of every unit (plus a final G)
+  int64_t xtab_size = 0;
+  bool quads = false;           // merge sibling pair groups into quads
+  bool thr_in_lds = true;       // thresholds searched in LDS (else in global memory)
   int hist_rounds = 2;          // histogram blocks per CU over the whole launch
-  DevBuf d_thr, d_thr_off, d_perm, d_thr_pad;
+  DevBuf d_thr, d_thr_off, d_perm, d_thr_pad, d_xunits;
 };
 
 // Per-class contraction shape: paths with dprime distinct features.
@@ -115,6 +120,7 @@ struct wdf_bg {
   double base = 0.0;
   wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)
   wdf::DevBuf d_tab;    // float gather tables
+  wdf::DevBuf d_xtab;   // explain tables of the specialised kernel (quads merged)
 };
 
 namespace wdf {

@@ -142,28 +142,64 @@ int make_plan(wdf_model *M) {
       P.thr_pad.push_back(i < K ? P.thr[(size_t)(P.thr_off[(size_t)f] + i)] : std::nanf(""));
   }
   while (P.thr_pad.size() % 4) P.thr_pad.push_back(std::nanf(""));
-  // LDS: thresholds plus two table stages within the 160 KB of a workgroup
+  // LDS: thresholds (when they are few enough) plus two table stages within
+  // the 160 KB of a workgroup; more thresholds are searched in global memory
   const int64_t lds_floats = 160 * 1024 / 4;
-  const int64_t room = (lds_floats - (int64_t)P.thr_pad.size()) / 2 / 4 * 4;
+  P.thr_in_lds = P.thr_pad.size() <= 8192;
+  const int64_t room = (lds_floats - (P.thr_in_lds ? (int64_t)P.thr_pad.size() : 0)) / 2 / 4 * 4;
   P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
   int max_table = 0;
   for (const Group &g : M->groups) max_table = std::max(max_table, ((g.depth << g.depth) + 3) / 4 * 4);
   if (P.stage_floats < max_table)
     return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %zu thresholds leave too little LDS for the tables",
                      P.thr_pad.size());
-  // explain stages: consecutive groups whose tables fit one LDS buffer
-  P.explain_stages.clear();
+  // explain-table units: a pair group and the next pair group form a quad
+  // when their pair nodes are the left and right children of one node
+  P.xunits.clear();
+  P.unit_g0.clear();
+  int64_t xoff = 0;
   for (int64_t g = 0; g < G;) {
-    int64_t a = g;
-    const int64_t t0 = M->groups[(size_t)g].tab_off;
-    while (g < G) {
-      const Group &gg = M->groups[(size_t)g];
-      const int64_t end = gg.tab_off + (((int64_t)gg.depth << gg.depth) + 3) / 4 * 4;
-      if (end - t0 > P.stage_floats) break;
-      ++g;
+    const Group &ga = M->groups[(size_t)g];
+    bool quad = false;
+    if (P.quads && g + 1 < G && ga.depth >= 2 && ga.col_r >= 0) {
+      const Group &gb = M->groups[(size_t)g + 1];
+      if (gb.depth == ga.depth && gb.col_r >= 0 && gb.tree == ga.tree) {
+        const size_t la = (size_t)ga.path_off + (size_t)ga.depth, lb = (size_t)gb.path_off + (size_t)gb.depth;
+        quad = M->path_nodes[la - 2] == M->path_nodes[lb - 2] && M->path[la - 2].dir == 0 && M->path[lb - 2].dir == 1;
+      }
     }
-    if (g == a) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: explain stage too small");
-    P.explain_stages.push_back({a, g});
+    if (quad && (((int64_t)(ga.depth + 1) << (ga.depth + 1)) + 3) / 4 * 4 > P.stage_floats) quad = false;
+    XUnit u{};
+    u.src_l = ga.tab_off;
+    u.src_r = quad ? M->groups[(size_t)g + 1].tab_off : -1;
+    u.dst = xoff;
+    u.depth = ga.depth;
+    u.quad = quad ? 1 : 0;
+    u.mask = 0;
+    for (int k = 0; k < (quad ? ga.depth - 2 : ga.depth); ++k)
+      u.mask = (u.mask << 1) | M->path[(size_t)ga.path_off + (size_t)k].dir;
+    const int64_t size = quad ? ((int64_t)(ga.depth + 1) << (ga.depth + 1)) : ((int64_t)ga.depth << ga.depth);
+    xoff += (size + 3) / 4 * 4;
+    P.xunits.push_back(u);
+    P.unit_g0.push_back(g);
+    g += quad ? 2 : 1;
+  }
+  P.unit_g0.push_back(G);
+  P.xtab_size = xoff;
+  // explain stages: consecutive units whose tables fit one LDS buffer (stored
+  // as group ranges; a stage never splits a quad)
+  P.explain_stages.clear();
+  const int64_t U = (int64_t)P.xunits.size();
+  auto unit_end = [&](int64_t u) {
+    const int64_t size = P.xunits[(size_t)u].quad ? ((int64_t)(P.xunits[(size_t)u].depth + 1) << (P.xunits[(size_t)u].depth + 1))
+                                                  : ((int64_t)P.xunits[(size_t)u].depth << P.xunits[(size_t)u].depth);
+    return P.xunits[(size_t)u].dst + (size + 3) / 4 * 4;
+  };
+  for (int64_t u = 0; u < U;) {
+    const int64_t a = u, t0 = P.xunits[(size_t)u].dst;
+    while (u < U && unit_end(u) - t0 <= P.stage_floats) ++u;
+    if (u == a) return set_error(WDF_E_UNSUPPORTED, "specialised kernels: explain stage too small");
+    P.explain_stages.push_back({P.unit_g0[(size_t)a], P.unit_g0[(size_t)u]});
   }
   return WDF_OK;
 }
@@ -184,6 +220,7 @@ typedef long long i64;
 struct TreeIndex {
   // per global node: group indices hanging off it, and the group range below it
   std::vector<int64_t> pair_of, single_l, single_r, gmin, gmax;
+  std::vector<int64_t> quad_of;  // unit index when the node roots a quad
   std::vector<int64_t> root_leaf_group;  // per tree, -1 if the root is inner
 };
 
@@ -196,6 +233,12 @@ TreeIndex index_tree_groups(const wdf_model *M) {
   ix.gmin.assign(N, INT64_MAX);
   ix.gmax.assign(N, -1);
   ix.root_leaf_group.assign((size_t)M->n_trees, -1);
+  ix.quad_of.assign(N, -1);
+  for (size_t u = 0; u < M->jp.xunits.size(); ++u) {
+    if (!M->jp.xunits[u].quad) continue;
+    const Group &g = M->groups[(size_t)M->jp.unit_g0[u]];
+    ix.quad_of[(size_t)M->path_nodes[(size_t)g.path_off + (size_t)g.depth - 2]] = (int64_t)u;
+  }
   for (size_t g = 0; g < M->groups.size(); ++g) {
     const Group &gr = M->groups[g];
     if (gr.depth == 0) {
@@ -231,29 +274,39 @@ struct Gen {
     return B[s];
   }
 
+  std::function<void(int64_t unit, const std::string &p)> on_quad;  // null: no quads
+
+  void test(int64_t nd, const std::string &pout, const std::string &pin) {
+    const int f = M->feature[(size_t)nd];
+    o << "u32 " << pout << "; " << (M->default_left[(size_t)nd] ? "NDS(" : "ND(") << pout << ", " << pin << ", w"
+      << f / M->jp.per_word << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] << ");\n";
+  }
+
   // depth-first over the nodes whose subtree holds groups of [a, b)
   void node(int64_t nd, const std::string &pin) {
     if (!(ix.gmin[(size_t)nd] < b && ix.gmax[(size_t)nd] >= a)) return;
-    const int f = M->feature[(size_t)nd];
-    const int j = M->jp.rank[(size_t)nd];
     const std::string pl = "p" + std::to_string(nd);
-    o << "u32 " << pl << "; " << (M->default_left[(size_t)nd] ? "NDS(" : "ND(") << pl << ", " << pin << ", w"
-      << f / M->jp.per_word << ", " << sel(f) << ", " << j << ");\n";
+    test(nd, pl, pin);
     const int64_t base = M->node_offset[(size_t)M->groups[(size_t)ix.gmin[(size_t)nd]].tree];
     const int64_t L = base + M->left[(size_t)nd], R = base + M->right[(size_t)nd];
+    if (on_quad && ix.quad_of[(size_t)nd] >= 0) {
+      // quad: index = ((2 P + s_a) * 2 + s_left) * 2 + s_right
+      const std::string il = "i" + std::to_string(nd), iq = "I" + std::to_string(nd);
+      test(L, il, pl);
+      test(R, iq, il);
+      on_quad(ix.quad_of[(size_t)nd], iq);
+      return;
+    }
     auto in = [&](int64_t g) { return g >= a && g < b; };
     if (ix.pair_of[(size_t)nd] >= 0) {
       if (in(ix.pair_of[(size_t)nd])) on_group(ix.pair_of[(size_t)nd], pl);
       return;
     }
+    // patterns carry raw splits: both children extend the same prefix
     if (ix.single_l[(size_t)nd] >= 0 && in(ix.single_l[(size_t)nd])) on_group(ix.single_l[(size_t)nd], pl);
-    if (ix.single_r[(size_t)nd] >= 0 && in(ix.single_r[(size_t)nd]))
-      on_group(ix.single_r[(size_t)nd], "(" + pl + " ^ 1u)");
+    if (ix.single_r[(size_t)nd] >= 0 && in(ix.single_r[(size_t)nd])) on_group(ix.single_r[(size_t)nd], pl);
     if (M->feature[(size_t)L] >= 0) node(L, pl);
-    if (M->feature[(size_t)R] >= 0 && ix.gmin[(size_t)R] < b && ix.gmax[(size_t)R] >= a) {
-      o << "u32 q" << nd << " = " << pl << " ^ 1u;\n";
-      node(R, "q" + std::to_string(nd));
-    }
+    if (M->feature[(size_t)R] >= 0) node(R, pl);
   }
 
   // every tree touching [a, b)
@@ -481,13 +534,13 @@ extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* _
                                                                   const float* __restrict__ thr,
                                                                   float* __restrict__ phi, i64 ldphi, i64 n, int live) {
   __shared__ __attribute__((aligned(16))) float lds[2 * SF];
-  __shared__ __attribute__((aligned(16))) float lthr[TF];
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
   const u32 zero = 0u;
-  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];
-  __syncthreads();
 )";
+  if (P.thr_in_lds)
+    o << "  __shared__ __attribute__((aligned(16))) float lthr[TF];\n"
+      << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
   for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
   // threshold ranks of the row, packed as the pattern kernels expect.  The
   // searches run step-major over batches of 16 features so that 16
@@ -511,7 +564,7 @@ extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* _
       for (size_t i = b0; i < b1; ++i) {
         const int f = uf[i];
         if (P.thr_steps[(size_t)f] <= k) continue;
-        o << " r" << f << " += (lthr[" << P.thr_pad_off[(size_t)f] + (1 << k) - 1 << " + r" << f << "] <= x" << f
+        o << " r" << f << " += (" << (P.thr_in_lds ? "lthr[" : "thr[") << P.thr_pad_off[(size_t)f] + (1 << k) - 1 << " + r" << f << "] <= x" << f
           << ") ? " << (1u << k) << "u : 0u;";
       }
       o << "\n";
@@ -530,12 +583,19 @@ extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* _
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
   const auto &S = P.explain_stages;
+  // unit of every group, and the explain-table span of a stage
+  std::vector<int64_t> unit_of(M->groups.size());
+  for (size_t u = 0; u + 1 < P.unit_g0.size(); ++u)
+    for (int64_t g = P.unit_g0[u]; g < P.unit_g0[u + 1]; ++g) unit_of[(size_t)g] = (int64_t)u;
+  auto unit_size = [&](int64_t u) {
+    const XUnit &x = P.xunits[(size_t)u];
+    const int64_t n = x.quad ? ((int64_t)(x.depth + 1) << (x.depth + 1)) : ((int64_t)x.depth << x.depth);
+    return (n + 3) / 4 * 4;
+  };
   auto stage_span = [&](size_t s, int64_t &t0, int64_t &n16) {
-    const Group &ga = M->groups[(size_t)S[s].first];
-    const Group &gb = M->groups[(size_t)S[s].second - 1];
-    t0 = ga.tab_off;
-    const int64_t t1 = gb.tab_off + (((int64_t)gb.depth << gb.depth) + 3) / 4 * 4;
-    n16 = (t1 - t0) / 4;
+    const int64_t ua = unit_of[(size_t)S[s].first], ub = unit_of[(size_t)S[s].second - 1];
+    t0 = P.xunits[(size_t)ua].dst;
+    n16 = (P.xunits[(size_t)ub].dst + unit_size(ub) - t0) / 4;
   };
   int64_t t0, n16;
   stage_span(0, t0, n16);
@@ -547,14 +607,28 @@ extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* _
       stage_span(s + 1, t0, n16);
       o << "  stage_copy(tab + " << t0 << ", lds + " << ((1 - buf) * P.stage_floats) << ", " << n16 << ");\n";
     }
-    const int64_t sbase = M->groups[(size_t)S[s].first].tab_off;
+    const int64_t sbase = P.xunits[(size_t)unit_of[(size_t)S[s].first]].dst;
     gen.on_group = [&](int64_t g, const std::string &p) {
       const Group &gr = M->groups[(size_t)g];
-      o << "{ const float* t = lds + " << (buf * P.stage_floats + (gr.tab_off - sbase)) << " + " << p << ";";
+      const XUnit &x = P.xunits[(size_t)unit_of[(size_t)g]];
+      o << "{ const float* t = lds + " << (buf * P.stage_floats + (x.dst - sbase)) << " + " << p << ";";
       for (int k = 0; k < gr.depth; ++k) {
         const PathNode &pn = M->path[(size_t)gr.path_off + k];
         if (!pn.first) continue;
         o << " f" << pn.feat << " += t[" << ((int64_t)k << gr.depth) << "];";
+      }
+      o << " }\n";
+    };
+    gen.on_quad = [&](int64_t u, const std::string &p) {
+      const XUnit &x = P.xunits[(size_t)u];
+      const Group &gl = M->groups[(size_t)P.unit_g0[(size_t)u]], &gr = M->groups[(size_t)P.unit_g0[(size_t)u] + 1];
+      const int d = x.depth;
+      const int64_t Q = (int64_t)2 << d;
+      o << "{ const float* t = lds + " << (buf * P.stage_floats + (x.dst - sbase)) << " + " << p << ";";
+      for (int v = 0; v <= d; ++v) {
+        const PathNode &pn = v < d ? M->path[(size_t)gl.path_off + v] : M->path[(size_t)gr.path_off + d - 1];
+        if (!pn.first) continue;
+        o << " f" << pn.feat << " += t[" << v * Q << "];";
       }
       o << " }\n";
     };
@@ -665,6 +739,10 @@ int jit_build(wdf_model *M) {
   if (!P.thr_pad.empty() && (e = hipMemcpyAsync(P.d_thr_pad.ptr, P.thr_pad.data(), P.thr_pad.size() * sizeof(float),
                                                 hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_error(e, "hipMemcpyAsync(padded thresholds)");
+  if ((rc = P.d_xunits.alloc(std::max<size_t>(P.xunits.size(), 1) * sizeof(XUnit)))) return rc;
+  if (!P.xunits.empty() && (e = hipMemcpyAsync(P.d_xunits.ptr, P.xunits.data(), P.xunits.size() * sizeof(XUnit),
+                                               hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(units)");
   if ((rc = P.d_perm.alloc(std::max<size_t>(P.perm.size(), 1) * sizeof(uint32_t)))) return rc;
   if (!P.perm.empty() && (e = hipMemcpyAsync(P.d_perm.ptr, P.perm.data(), P.perm.size() * sizeof(uint32_t),
                                              hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -704,7 +782,7 @@ int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *his
 int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s) {
   const wdf_model *M = bg->model;
   const JitPlan &P = M->jp;
-  const float *tab = bg->d_tab.as<float>();
+  const float *tab = bg->d_xtab.as<float>();
   const float *thr = P.d_thr_pad.as<float>();
   int live = 1;
   void *args[] = {(void *)&X, &ldx, (void *)&tab, (void *)&thr, &phi, &ldphi, &n, &live};

@@ -35,6 +35,7 @@ BANZHAF = 1
 KERNEL_AUTO = 0
 KERNEL_GENERIC = 1
 KERNEL_SPECIALISED = 2
+KERNEL_QUADS = 16          # flag: merged sibling-pair tables in the specialised gather
 
 MAX_DEPTH = 8
 SERVE_ONE_PER_LAUNCH = 1
@@ -124,7 +125,7 @@ def lib():
         L.wdf_debug_histograms.restype = I64
         L.wdf_debug_tables.argtypes = [P, P, I64]
         L.wdf_debug_tables.restype = I64
-        L.wdf_debug_specialised_source.argtypes = [P, I, P, I64]
+        L.wdf_debug_specialised_source.argtypes = [P, I, I, P, I64]
         L.wdf_debug_specialised_source.restype = I64
         L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
@@ -172,13 +173,13 @@ def _model_desc(ens, with_cover=True):
     return desc, keep
 
 
-def specialised_source(ens, compile: bool = False) -> str:
+def specialised_source(ens, compile: bool = False, kernel: int = KERNEL_SPECIALISED) -> str:
     """Generated source of the model-specialised kernels (no GPU needed);
     with compile=True also compiles it for gfx950 with hipRTC."""
     desc, keep = _model_desc(ens)
-    n = _check(lib().wdf_debug_specialised_source(C.byref(desc), int(compile), None, 0))
+    n = _check(lib().wdf_debug_specialised_source(C.byref(desc), kernel, int(compile), None, 0))
     buf = C.create_string_buffer(n + 1)
-    _check(lib().wdf_debug_specialised_source(C.byref(desc), 0, buf, n + 1))
+    _check(lib().wdf_debug_specialised_source(C.byref(desc), kernel, 0, buf, n + 1))
     return buf.value.decode()
 
 

@@ -34,17 +34,18 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
 
 
-KERNELS = ["generic", "auto"]
+KERNELS = ["generic", "auto", "quads"]
 
 
 def _kernel(wdf, name):
-    return {"generic": wdf.KERNEL_GENERIC, "auto": wdf.KERNEL_AUTO}[name]
+    return {"generic": wdf.KERNEL_GENERIC, "auto": wdf.KERNEL_AUTO,
+            "quads": wdf.KERNEL_AUTO | wdf.KERNEL_QUADS}[name]
 
 
 def _load(wdf, ctx, ens, kname):
-    """Load a model; with kname "auto" the specialised kernels must be the ones in use."""
+    """Load a model; with kname "auto" or "quads" the specialised kernels must be the ones in use."""
     model = wdf.Model(ctx, ens, _kernel(wdf, kname))
-    assert model.specialised == (kname == "auto"), f"kernel choice {kname}: specialised={model.specialised}"
+    assert model.specialised == (kname != "generic"), f"kernel choice {kname}: specialised={model.specialised}"
     return model
 
 
