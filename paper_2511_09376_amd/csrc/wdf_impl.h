@@ -54,7 +54,8 @@ struct JitPlan {
   bool quads = false;           // merge sibling pair groups into quads
   bool thr_in_lds = true;       // thresholds searched in LDS (else in global memory)
   int hist_rounds = 2;          // histogram blocks per CU over the whole launch
-  DevBuf d_thr, d_thr_off, d_perm, d_thr_pad, d_xunits;
+  std::vector<int32_t> pad_meta;  // per feature: thr_pad offset, steps (the quantizer's view)
+  DevBuf d_pad_meta, d_perm, d_thr_pad, d_xunits;
 };
 
 // Per-class contraction shape: paths with dprime distinct features.

@@ -726,15 +726,18 @@ int jit_build(wdf_model *M) {
   }
   JitPlan &P = M->jp;
   hipStream_t s = M->ctx->stream;
-  if ((rc = P.d_thr.alloc(std::max<size_t>(P.thr.size(), 1) * sizeof(float)))) return rc;
-  if ((rc = P.d_thr_off.alloc(P.thr_off.size() * sizeof(int32_t)))) return rc;
+  // per feature: (offset in the padded thresholds, search steps); 0 steps for unused features
+  P.pad_meta.assign((size_t)M->n_features * 2, 0);
+  for (int f = 0; f < M->n_features; ++f)
+    if (P.thr_steps[(size_t)f] > 0) {
+      P.pad_meta[2 * (size_t)f] = P.thr_pad_off[(size_t)f];
+      P.pad_meta[2 * (size_t)f + 1] = P.thr_steps[(size_t)f];
+    }
+  if ((rc = P.d_pad_meta.alloc(P.pad_meta.size() * sizeof(int32_t)))) return rc;
   hipError_t e;
-  if (!P.thr.empty() &&
-      (e = hipMemcpyAsync(P.d_thr.ptr, P.thr.data(), P.thr.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_error(e, "hipMemcpyAsync(thresholds)");
-  if ((e = hipMemcpyAsync(P.d_thr_off.ptr, P.thr_off.data(), P.thr_off.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                          s)) != hipSuccess)
-    return hip_error(e, "hipMemcpyAsync(threshold offsets)");
+  if ((e = hipMemcpyAsync(P.d_pad_meta.ptr, P.pad_meta.data(), P.pad_meta.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(e, "hipMemcpyAsync(threshold blocks)");
   if ((rc = P.d_thr_pad.alloc(std::max<size_t>(P.thr_pad.size(), 1) * sizeof(float)))) return rc;
   if (!P.thr_pad.empty() && (e = hipMemcpyAsync(P.d_thr_pad.ptr, P.thr_pad.data(), P.thr_pad.size() * sizeof(float),
                                                 hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -757,7 +760,7 @@ int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *his
   DevBuf &codes = M->ws_codes;  // the caller holds the model's workspace lock
   int rc;
   if ((rc = ws_reserve(codes, (size_t)P.words * (size_t)m * sizeof(uint32_t)))) return rc;
-  hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr.as<float>(), P.d_thr_off.as<int32_t>(), P.wide,
+  hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr_pad.as<float>(), P.d_pad_meta.as<int2>(), P.wide,
                                  P.words, codes.as<uint32_t>(), m, s);
   if (e != hipSuccess) return hip_error(e, "quantize");
   // one block per CU at a time (the LDS histogram); a whole number of rounds

@@ -298,52 +298,86 @@ hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *r
 // the code with only the top bit set (0x80 / 0x8000): it compares below every
 // rank as a signed number and above every rank as an unsigned one, which the
 // kernels use to send it to the node's default side.
-// One block: one word, kQuantRows rows.  The word's thresholds are staged in
-// LDS when they fit; the search takes the same number of steps in every lane.
+// One block: one word, kQuantRows rows; one thread runs the (up to four)
+// searches of a row's word side by side.  Each used feature's thresholds are
+// padded with NaN to 2^c entries (c = meta[f].y, offset meta[f].x), so its
+// search takes exactly c steps in every lane and never leaves the feature's
+// block: NaN never compares <= x.  The word's blocks are contiguous and are
+// staged in LDS when they fit.
 constexpr int kQuantRows = 2048;
 constexpr int kQuantLds = 4096;
 
-__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t n, int64_t ldx, int F,
-                                                  const float *__restrict__ thr, const int32_t *__restrict__ thr_off,
-                                                  int wide, uint32_t *codes, int64_t ldc) {
-  __shared__ float st[kQuantLds];
-  const int w = blockIdx.y;
-  const int per = wide ? 2 : 4, bits = wide ? 16 : 8;
-  const int f0 = w * per, f1 = min(F, f0 + per);
-  const int lo = thr_off[f0], hi = thr_off[f1];
-  const bool staged = hi - lo <= kQuantLds;
-  if (staged)
-    for (int i = threadIdx.x; i < hi - lo; i += 256) st[i] = thr[lo + i];
-  __syncthreads();
-  // thresholds of this word's features, indexed from the first one (both
-  // pointers stay inside their arrays)
-  const float *T = staged ? st : thr + lo;
+// the rows of one block; T is the word's thresholds (LDS or global memory),
+// off[k] the block of its k-th feature inside T
+__device__ __forceinline__ void quantize_rows(const float *__restrict__ T, const int (&off)[4], const int (&c)[4],
+                                              int cmax, const float *__restrict__ X, int64_t n, int64_t ldx, int f0,
+                                              int nf, int bits, uint32_t *__restrict__ out) {
+  const uint32_t nan_code = 1u << (bits - 1);
   const int64_t r0 = (int64_t)blockIdx.x * kQuantRows;
   for (int64_t r = r0 + threadIdx.x; r < r0 + kQuantRows && r < n; r += 256) {
-    uint32_t word = 0;
-    for (int f = f0; f < f1; ++f) {
-      const float x = X[(int64_t)f * ldx + r];
-      const int b = thr_off[f] - lo, K = thr_off[f + 1] - thr_off[f];
-      uint32_t code;
-      if (x != x) {
-        code = 1u << (bits - 1);
-      } else {
-        int pos = 0;  // thresholds known to be <= x
-        for (int step = K ? (1 << (31 - __builtin_clz((unsigned)K))) : 0; step > 0; step >>= 1)
-          if (pos + step <= K && T[b + pos + step - 1] <= x) pos += step;
-        code = (uint32_t)pos;
-      }
-      word |= code << ((f - f0) * bits);
+    float x[4];
+    int p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = k < nf ? X[(int64_t)(f0 + k) * ldx + r] : 0.f;
+      p[k] = 0;
     }
-    codes[(int64_t)w * ldc + r] = word;
+    for (int sidx = cmax - 1; sidx >= 0; --sidx) {
+      // the four searches load unconditionally (a feature past its last step
+      // re-reads its own first threshold and ignores it), so the loads overlap
+      const int step = 1 << sidx;
+      float t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = T[sidx < c[k] ? off[k] + p[k] + step - 1 : off[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] += (sidx < c[k] && t[k] <= x[k]) ? step : 0;
+    }
+    uint32_t word = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < nf) word |= (x[k] != x[k] ? nan_code : (uint32_t)p[k]) << (k * bits);
+    out[r] = word;
   }
 }
 
-hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr, const int32_t *thr_off,
+__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t n, int64_t ldx, int F,
+                                                  const float *__restrict__ thr_pad, const int2 *__restrict__ meta,
+                                                  int wide, uint32_t *__restrict__ codes, int64_t ldc) {
+  __shared__ float st[kQuantLds];
+  const int w = blockIdx.y;
+  const int per = wide ? 2 : 4, bits = wide ? 16 : 8;
+  const int f0 = w * per, nf = min(F - f0, per);
+  int off[4], c[4];
+  int lo = 0x7fffffff, hi = 0, cmax = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int2 mk = k < nf ? meta[f0 + k] : make_int2(0, 0);
+    off[k] = mk.x;
+    c[k] = mk.y;
+    if (mk.y > 0) {
+      lo = min(lo, mk.x);
+      hi = max(hi, mk.x + (1 << mk.y));
+      cmax = max(cmax, mk.y);
+    }
+  }
+  if (cmax == 0) lo = hi = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) off[k] = c[k] > 0 ? off[k] - lo : 0;
+  uint32_t *out = codes + (int64_t)w * ldc;
+  if (hi - lo <= kQuantLds) {
+    for (int i = threadIdx.x; i < hi - lo; i += 256) st[i] = thr_pad[lo + i];
+    __syncthreads();
+    quantize_rows(st, off, c, cmax, X, n, ldx, f0, nf, bits, out);
+  } else {
+    quantize_rows(thr_pad + lo, off, c, cmax, X, n, ldx, f0, nf, bits, out);
+  }
+}
+
+hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr_pad, const int2 *meta,
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + kQuantRows - 1) / kQuantRows), (unsigned)words), dim3(256), 0, s,
-                     X, n, ldx, F, thr, thr_off, wide, codes, ldc);
+                     X, n, ldx, F, thr_pad, meta, wide, codes, ldc);
   return hipGetLastError();
 }
 
