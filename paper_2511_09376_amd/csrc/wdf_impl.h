@@ -40,6 +40,7 @@ struct JitPlan {
   std::vector<int32_t> thr_off; // n_features + 1
   std::vector<int32_t> rank;    // per node: index of its threshold among its feature's
   int nt_hist = 512, nt_explain = 512;
+  int explain_bpc = 1;           // explain blocks per CU sharing the LDS (512 / bpc threads each)
   int hist_cap = 32768;         // uint32 counters per histogram chunk (LDS)
   int stage_floats_max = 12288; // table floats per explain stage (LDS, double-buffered)
   int stage_floats = 12288;     // the same after room for the thresholds

@@ -146,7 +146,8 @@ int make_plan(wdf_model *M) {
   // the 160 KB of a workgroup; more thresholds are searched in global memory
   const int64_t lds_floats = 160 * 1024 / 4;
   P.thr_in_lds = P.thr_pad.size() <= 8192;
-  const int64_t room = (lds_floats - (P.thr_in_lds ? (int64_t)P.thr_pad.size() : 0)) / 2 / 4 * 4;
+  P.nt_explain = 512 / P.explain_bpc;
+  const int64_t room = (lds_floats / P.explain_bpc - (P.thr_in_lds ? (int64_t)P.thr_pad.size() : 0)) / 2 / 4 * 4;
   P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
   int max_table = 0;
   for (const Group &g : M->groups) max_table = std::max(max_table, ((g.depth << g.depth) + 3) / 4 * 4);
@@ -211,10 +212,13 @@ int make_plan(wdf_model *M) {
 const char *kPreamble = R"(
 typedef unsigned int u32;
 typedef long long i64;
-// node test on a threshold rank (unsigned: NaN goes right; signed: NaN goes left),
-// then pattern update P' = 2 P + split through the carry
-#define ND(po, pi, w, sel, j) asm("v_cmp_le_u32_sdwa vcc, %1, %2 src0_sel:" sel " src1_sel:DWORD\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc" : "=v"(po) : "v"(w), "s"(j), "v"(pi) : "vcc")
-#define NDS(po, pi, w, sel, j) asm("v_cmp_le_i32_sdwa vcc, sext(%1), %2 src0_sel:" sel " src1_sel:DWORD\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc" : "=v"(po) : "v"(w), "s"(j), "v"(pi) : "vcc")
+// Node test on a threshold rank: t = rank - (j + 1) is negative exactly when
+// rank <= j, i.e. when the row goes left (TU: rank unsigned, so a NaN goes
+// right; TS: rank sign-extended, so a NaN goes left).  The caller shifts t's
+// sign bit into the pattern with alignbit: P' = 2 P + split.  The constant is
+// moved into an SGPR inside the asm, so it is not a loop-invariant register.
+#define TU(t, w, sel, j1) do { u32 s_; asm("s_mov_b32 %1, " #j1 "\n\tv_sub_u32_sdwa %0, %2, %1 src0_sel:" sel " src1_sel:DWORD" : "=v"(t), "=&s"(s_) : "v"(w)); } while (0)
+#define TS(t, w, sel, j1) do { u32 s_; asm("s_mov_b32 %1, " #j1 "\n\tv_sub_u32_sdwa %0, sext(%2), %1 src0_sel:" sel " src1_sel:DWORD" : "=v"(t), "=&s"(s_) : "v"(w)); } while (0)
 )";
 
 struct TreeIndex {
@@ -278,8 +282,9 @@ struct Gen {
 
   void test(int64_t nd, const std::string &pout, const std::string &pin) {
     const int f = M->feature[(size_t)nd];
-    o << "u32 " << pout << "; " << (M->default_left[(size_t)nd] ? "NDS(" : "ND(") << pout << ", " << pin << ", w"
-      << f / M->jp.per_word << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] << ");\n";
+    o << "u32 " << pout << "; { u32 t_; " << (M->default_left[(size_t)nd] ? "TS(" : "TU(") << "t_, w"
+      << f / M->jp.per_word << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] + 1 << "); " << pout
+      << " = __builtin_amdgcn_alignbit(" << pin << ", t_, 31); }\n";
   }
 
   // depth-first over the nodes whose subtree holds groups of [a, b)
@@ -529,19 +534,21 @@ __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float*
                                        (__attribute__((address_space(3))) void*)(dst + 4 * c), 16, 0, 0);
   }
 }
-extern "C" __global__ __launch_bounds__(NT) void wdf_explain_spec(const float* __restrict__ X, i64 ldx,
-                                                                  const float* __restrict__ tab,
-                                                                  const float* __restrict__ thr,
-                                                                  float* __restrict__ phi, i64 ldphi, i64 n, int live) {
+// one row per lane, one tile of NT rows per block
+extern "C" __global__ __launch_bounds__(NT, 2) void wdf_explain_spec(const float* __restrict__ X, i64 ldx,
+                                                                     const float* __restrict__ tab,
+                                                                     const float* __restrict__ thr,
+                                                                     float* __restrict__ phi, i64 ldphi, i64 n, int live) {
   __shared__ __attribute__((aligned(16))) float lds[2 * SF];
+  const u32 zero = 0u;
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
-  const u32 zero = 0u;
 )";
   if (P.thr_in_lds)
     o << "  __shared__ __attribute__((aligned(16))) float lthr[TF];\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
   for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
+
   // threshold ranks of the row, packed as the pattern kernels expect.  The
   // searches run step-major over batches of 16 features so that 16
   // independent LDS reads are in flight at every step.
