@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="paper", choices=list(DESCRIPTIONS))
-    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialised"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialised", "pairs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
@@ -178,7 +178,8 @@ def main():
     print(f"[bench] generated {args.workload}: {ens.n_trees} trees, X {X.shape}, B {B.shape} "
           f"in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
-    kernel = {"auto": wdf.KERNEL_AUTO, "generic": wdf.KERNEL_GENERIC, "specialised": wdf.KERNEL_SPECIALISED}[args.kernel]
+    kernel = {"auto": wdf.KERNEL_AUTO, "generic": wdf.KERNEL_GENERIC, "specialised": wdf.KERNEL_SPECIALISED,
+              "pairs": wdf.KERNEL_AUTO | wdf.KERNEL_PAIRS}[args.kernel]
     ctx = wdf.Context(0)
     t0 = time.perf_counter()
     model = wdf.Model(ctx, ens, kernel)

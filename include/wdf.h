@@ -65,12 +65,12 @@ enum {
   WDF_KERNEL_AUTO = 0,      /* model-specialised kernels when they compile, else generic */
   WDF_KERNEL_GENERIC = 1,   /* data-driven kernels that walk each leaf path */
   WDF_KERNEL_SPECIALISED = 2,/* kernels compiled for this ensemble at load time (hipRTC) */
-  /* Flag, OR-ed into AUTO or SPECIALISED: the specialised gather reads the two
-   * sibling pairs below a node from one merged table ("quad", d + 1 values at
-   * 2^(d+1) entries) instead of two pair tables (2 x d values at 2^d entries):
-   * fewer reads and adds, larger tables, so more LDS bank conflicts.  Results
-   * are the same sums in another order. */
-  WDF_KERNEL_QUADS = 16
+  /* Flag, OR-ed into AUTO or SPECIALISED: the specialised gather reads every
+   * sibling pair from its own table (d values at 2^d entries) instead of
+   * merging the two pairs below a node into one "quad" table (d + 1 values at
+   * 2^(d+1) entries), the default.  Results are the same sums in another
+   * order. */
+  WDF_KERNEL_PAIRS = 16
 };
 
 typedef struct wdf_ctx wdf_ctx;
@@ -105,7 +105,7 @@ typedef struct {
  * extract its root-to-leaf paths, pair sibling leaves, build the
  * pattern-to-coefficient matrices in double precision and upload everything to
  * the context's device.  `kernel` is one of WDF_KERNEL_AUTO, _GENERIC,
- * _SPECIALISED, optionally OR-ed with WDF_KERNEL_QUADS; with AUTO or
+ * _SPECIALISED, optionally OR-ed with WDF_KERNEL_PAIRS; with AUTO or
  * SPECIALISED the pattern/histogram/gather kernels are generated for this
  * ensemble and compiled with hipRTC (cached per source).
  * Errors: INVALID_ARG (cycles, bad child or feature index, n_features < 1),
@@ -174,7 +174,7 @@ int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap);
  * enough; the return value is the source length) and, with compile != 0, also
  * compile it for gfx950 with hipRTC (COMPILE on failure, the log in
  * wdf_last_error()).  `kernel` takes the flags of wdf_model_load (only
- * WDF_KERNEL_QUADS matters here).  For tools and tests; needs no GPU. */
+ * WDF_KERNEL_PAIRS matters here).  For tools and tests; needs no GPU. */
 int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int compile, char *out, int64_t cap);
 
 /* ---- serving: continuous batching of explain requests ------------------- */

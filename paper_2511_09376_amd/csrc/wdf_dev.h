@@ -34,15 +34,23 @@ struct Group {
 // child) with d + 1 values per entry (d = the pairs' depth).  Explain tables
 // are indexed by raw splits (bit 1: the row went left), not by whether the row
 // follows the path; `mask` holds the path's right turns, so the pattern of a
-// raw index r is r ^ mask.
+// raw index r is r ^ mask.  Layout: E = 2^(depth + quad) entries of nv values,
+// stored as ceil(nv / 4) float4 planes [plane][entry], value v in component
+// v % 4 of plane v / 4 (unused components 0), so that one 16-byte LDS read
+// returns four values of an entry.
 struct XUnit {
   int64_t src_l;   // table offset of the (left) group
   int64_t src_r;   // table offset of the right pair group of a quad, -1 otherwise
-  int64_t dst;     // offset in the explain tables
+  int64_t dst;     // offset in the explain tables (floats, multiple of 4)
   int32_t depth;   // depth of the group(s)
   int32_t quad;    // 1 for a quad
   uint32_t mask;   // right turns: all d positions of a group, the d - 2 prefix positions of a quad
-  uint32_t pad_;
+  int32_t nv;      // values per entry: depth + quad
 };
+
+// floats of a unit in the explain tables
+inline int64_t xunit_floats(const XUnit &u) {
+  return 4 * (int64_t)((u.nv + 3) / 4) * ((int64_t)1 << (u.depth + u.quad));
+}
 
 }  // namespace wdf

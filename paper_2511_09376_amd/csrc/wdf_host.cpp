@@ -391,8 +391,8 @@ static int upload_model(wdf_model *M) {
 extern "C" int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out) {
   if (!ctx || !desc || !out) return set_error(WDF_E_INVALID_ARG, "wdf_model_load: NULL argument");
   *out = nullptr;
-  const bool quads = (kernel & WDF_KERNEL_QUADS) != 0;
-  kernel &= ~WDF_KERNEL_QUADS;
+  const bool quads = (kernel & WDF_KERNEL_PAIRS) == 0;
+  kernel &= ~WDF_KERNEL_PAIRS;
   if (kernel < WDF_KERNEL_AUTO || kernel > WDF_KERNEL_SPECIALISED)
     return set_error(WDF_E_INVALID_ARG, "wdf_model_load: unknown kernel choice %d", kernel);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -629,7 +629,7 @@ extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int 
     wdf_model M;
     int rc = validate_and_layout(desc, &M);
     if (rc) return rc;
-    M.jp.quads = (kernel & WDF_KERNEL_QUADS) != 0;
+    M.jp.quads = (kernel & WDF_KERNEL_PAIRS) == 0;
     std::string src;
     if ((rc = jit_source(&M, do_compile != 0, src))) return rc;
     if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);

@@ -52,7 +52,7 @@ struct JitPlan {
   std::vector<XUnit> xunits;    // explain-table units in group order
   std::vector<int64_t> unit_g0; // first group of every unit (plus a final G)
   int64_t xtab_size = 0;
-  bool quads = false;           // merge sibling pair groups into quads
+  bool quads = true;            // merge sibling pair groups into quads
   bool thr_in_lds = true;       // thresholds searched in LDS (else in global memory)
   int hist_rounds = 2;          // histogram blocks per CU over the whole launch
   std::vector<int32_t> pad_meta;  // per feature: thr_pad offset, steps (the quantizer's view)

@@ -150,7 +150,7 @@ int make_plan(wdf_model *M) {
   const int64_t room = (lds_floats / P.explain_bpc - (P.thr_in_lds ? (int64_t)P.thr_pad.size() : 0)) / 2 / 4 * 4;
   P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
   int max_table = 0;
-  for (const Group &g : M->groups) max_table = std::max(max_table, ((g.depth << g.depth) + 3) / 4 * 4);
+  for (const Group &g : M->groups) max_table = std::max(max_table, 4 * ((g.depth + 3) / 4) << g.depth);
   if (P.stage_floats < max_table)
     return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %zu thresholds leave too little LDS for the tables",
                      P.thr_pad.size());
@@ -169,18 +169,23 @@ int make_plan(wdf_model *M) {
         quad = M->path_nodes[la - 2] == M->path_nodes[lb - 2] && M->path[la - 2].dir == 0 && M->path[lb - 2].dir == 1;
       }
     }
-    if (quad && (((int64_t)(ga.depth + 1) << (ga.depth + 1)) + 3) / 4 * 4 > P.stage_floats) quad = false;
     XUnit u{};
     u.src_l = ga.tab_off;
     u.src_r = quad ? M->groups[(size_t)g + 1].tab_off : -1;
     u.dst = xoff;
     u.depth = ga.depth;
     u.quad = quad ? 1 : 0;
+    u.nv = ga.depth + u.quad;
+    if (quad && xunit_floats(u) > P.stage_floats) {
+      quad = false;
+      u.src_r = -1;
+      u.quad = 0;
+      u.nv = ga.depth;
+    }
     u.mask = 0;
     for (int k = 0; k < (quad ? ga.depth - 2 : ga.depth); ++k)
       u.mask = (u.mask << 1) | M->path[(size_t)ga.path_off + (size_t)k].dir;
-    const int64_t size = quad ? ((int64_t)(ga.depth + 1) << (ga.depth + 1)) : ((int64_t)ga.depth << ga.depth);
-    xoff += (size + 3) / 4 * 4;
+    xoff += xunit_floats(u);
     P.xunits.push_back(u);
     P.unit_g0.push_back(g);
     g += quad ? 2 : 1;
@@ -191,11 +196,7 @@ int make_plan(wdf_model *M) {
   // as group ranges; a stage never splits a quad)
   P.explain_stages.clear();
   const int64_t U = (int64_t)P.xunits.size();
-  auto unit_end = [&](int64_t u) {
-    const int64_t size = P.xunits[(size_t)u].quad ? ((int64_t)(P.xunits[(size_t)u].depth + 1) << (P.xunits[(size_t)u].depth + 1))
-                                                  : ((int64_t)P.xunits[(size_t)u].depth << P.xunits[(size_t)u].depth);
-    return P.xunits[(size_t)u].dst + (size + 3) / 4 * 4;
-  };
+  auto unit_end = [&](int64_t u) { return P.xunits[(size_t)u].dst + xunit_floats(P.xunits[(size_t)u]); };
   for (int64_t u = 0; u < U;) {
     const int64_t a = u, t0 = P.xunits[(size_t)u].dst;
     while (u < U && unit_end(u) - t0 <= P.stage_floats) ++u;
@@ -524,7 +525,8 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   std::vector<char> used((size_t)F, 0);
   for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
   o << kPreamble;
-  o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n";
+  o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n"
+    << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
   o << R"(
 __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float* dst, int n16) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -594,11 +596,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void wdf_explain_spec(const float
   std::vector<int64_t> unit_of(M->groups.size());
   for (size_t u = 0; u + 1 < P.unit_g0.size(); ++u)
     for (int64_t g = P.unit_g0[u]; g < P.unit_g0[u + 1]; ++g) unit_of[(size_t)g] = (int64_t)u;
-  auto unit_size = [&](int64_t u) {
-    const XUnit &x = P.xunits[(size_t)u];
-    const int64_t n = x.quad ? ((int64_t)(x.depth + 1) << (x.depth + 1)) : ((int64_t)x.depth << x.depth);
-    return (n + 3) / 4 * 4;
-  };
+  auto unit_size = [&](int64_t u) { return xunit_floats(P.xunits[(size_t)u]); };
   auto stage_span = [&](size_t s, int64_t &t0, int64_t &n16) {
     const int64_t ua = unit_of[(size_t)S[s].first], ub = unit_of[(size_t)S[s].second - 1];
     t0 = P.xunits[(size_t)ua].dst;
@@ -615,29 +613,41 @@ extern "C" __global__ __launch_bounds__(NT, 2) void wdf_explain_spec(const float
       o << "  stage_copy(tab + " << t0 << ", lds + " << ((1 - buf) * P.stage_floats) << ", " << n16 << ");\n";
     }
     const int64_t sbase = P.xunits[(size_t)unit_of[(size_t)S[s].first]].dst;
-    gen.on_group = [&](int64_t g, const std::string &p) {
-      const Group &gr = M->groups[(size_t)g];
-      const XUnit &x = P.xunits[(size_t)unit_of[(size_t)g]];
-      o << "{ const float* t = lds + " << (buf * P.stage_floats + (x.dst - sbase)) << " + " << p << ";";
-      for (int k = 0; k < gr.depth; ++k) {
-        const PathNode &pn = M->path[(size_t)gr.path_off + k];
-        if (!pn.first) continue;
-        o << " f" << pn.feat << " += t[" << ((int64_t)k << gr.depth) << "];";
+    // one 16-byte read per float4 plane returns four values of the entry;
+    // value v adds to the feature of its path position when that position is
+    // the feature's first on the path.  The empty asm takes all four lanes of
+    // the read, so a plane with unused components is not narrowed to an 8- or
+    // 12-byte read, which costs more LDS cycles per value on random addresses.
+    auto gather = [&](const XUnit &x, const std::string &p, const std::vector<const PathNode *> &pos) {
+      const int64_t E = (int64_t)1 << (x.depth + x.quad);
+      o << "{ const vf4* t = (const vf4*)(lds + " << (buf * P.stage_floats + (x.dst - sbase)) << ") + " << p << ";";
+      static const char *C[4] = {"x", "y", "z", "w"};
+      for (int j = 0; 4 * j < x.nv; ++j) {
+        bool any = false;
+        for (int c = 0; c < 4 && 4 * j + c < x.nv; ++c) any = any || pos[(size_t)(4 * j + c)]->first;
+        if (!any) continue;
+        o << " { vf4 a = t[" << j * E << "]; asm(\"\" : \"+v\"(a));";
+        for (int c = 0; c < 4 && 4 * j + c < x.nv; ++c) {
+          const PathNode *pn = pos[(size_t)(4 * j + c)];
+          if (pn->first) o << " f" << pn->feat << " += a." << C[c] << ";";
+        }
+        o << " }";
       }
       o << " }\n";
+    };
+    gen.on_group = [&](int64_t g, const std::string &p) {
+      const Group &gr = M->groups[(size_t)g];
+      std::vector<const PathNode *> pos;
+      for (int k = 0; k < gr.depth; ++k) pos.push_back(&M->path[(size_t)gr.path_off + k]);
+      gather(P.xunits[(size_t)unit_of[(size_t)g]], p, pos);
     };
     gen.on_quad = [&](int64_t u, const std::string &p) {
       const XUnit &x = P.xunits[(size_t)u];
       const Group &gl = M->groups[(size_t)P.unit_g0[(size_t)u]], &gr = M->groups[(size_t)P.unit_g0[(size_t)u] + 1];
-      const int d = x.depth;
-      const int64_t Q = (int64_t)2 << d;
-      o << "{ const float* t = lds + " << (buf * P.stage_floats + (x.dst - sbase)) << " + " << p << ";";
-      for (int v = 0; v <= d; ++v) {
-        const PathNode &pn = v < d ? M->path[(size_t)gl.path_off + v] : M->path[(size_t)gr.path_off + d - 1];
-        if (!pn.first) continue;
-        o << " f" << pn.feat << " += t[" << v * Q << "];";
-      }
-      o << " }\n";
+      std::vector<const PathNode *> pos;
+      for (int v = 0; v < x.depth; ++v) pos.push_back(&M->path[(size_t)gl.path_off + v]);
+      pos.push_back(&M->path[(size_t)gr.path_off + x.depth - 1]);
+      gather(x, p, pos);
     };
     o << "  {\n";
     gen.range(S[s].first, S[s].second);

@@ -381,8 +381,8 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
   return hipGetLastError();
 }
 
-// Explain tables from the gather tables: units copied as is, or quads built
-// from their two pair tables.  For a quad of pair depth d, entry I (d+1 bits:
+// Explain tables from the gather tables: each unit re-indexed by raw splits
+// and laid out in float4 planes; quads built from their two pair tables.  For a quad of pair depth d, entry I (d+1 bits:
 // prefix, s_a, s_aL, s_aR) has the left pair pattern (prefix, s_a, s_aL) and
 // the right pair pattern (prefix, !s_a, s_aR); value v < d-1 sums both pairs
 // at path position v, v = d-1 is the left pair's last position, v = d the
@@ -390,26 +390,26 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
 __global__ __launch_bounds__(256) void k_xtab(const XUnit *__restrict__ units, const float *__restrict__ tab,
                                               float *__restrict__ xtab) {
   const XUnit u = units[blockIdx.x];
-  const int d = u.depth;
-  if (!u.quad) {
-    const int n = d << d, P = 1 << d;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-      xtab[u.dst + i] = tab[u.src_l + (i & ~(P - 1)) + ((i & (P - 1)) ^ (int)u.mask)];
-    return;
-  }
-  const int P = 1 << d, Q = 2 << d;
+  const int d = u.depth, P = 1 << d;
+  const int E = 1 << (d + u.quad), planes = (u.nv + 3) / 4;
   const float *tl = tab + u.src_l, *tr = tab + u.src_r;
-  for (int i = threadIdx.x; i < (d + 1) * Q; i += blockDim.x) {
-    const int v = i / Q, I = i % Q;
-    // raw splits: the node and its left child go left on the left pair's path,
-    // the node goes right and its right child left on the right pair's path
-    const int prefix = (I >> 3) ^ (int)u.mask, sa = (I >> 2) & 1, sl = (I >> 1) & 1, sr = I & 1;
-    const int pl = (prefix << 2) | (sa << 1) | sl;
-    const int pr = (prefix << 2) | ((1 - sa) << 1) | sr;
-    float val;
-    if (v < d - 1) val = tl[v * P + pl] + tr[v * P + pr];
-    else if (v == d - 1) val = tl[(d - 1) * P + pl];
-    else val = tr[(d - 1) * P + pr];
+  for (int i = threadIdx.x; i < planes * E * 4; i += blockDim.x) {
+    const int v = (i / (4 * E)) * 4 + (i & 3), I = (i / 4) % E;
+    float val = 0.f;
+    if (v < u.nv) {
+      if (!u.quad) {
+        val = tl[v * P + (I ^ (int)u.mask)];
+      } else {
+        // raw splits: the node and its left child go left on the left pair's
+        // path, the node goes right and its right child left on the right pair's
+        const int prefix = (I >> 3) ^ (int)u.mask, sa = (I >> 2) & 1, sl = (I >> 1) & 1, sr = I & 1;
+        const int pl = (prefix << 2) | (sa << 1) | sl;
+        const int pr = (prefix << 2) | ((1 - sa) << 1) | sr;
+        if (v < d - 1) val = tl[v * P + pl] + tr[v * P + pr];
+        else if (v == d - 1) val = tl[(d - 1) * P + pl];
+        else val = tr[(d - 1) * P + pr];
+      }
+    }
     xtab[u.dst + i] = val;
   }
 }

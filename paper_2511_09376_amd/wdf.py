@@ -35,7 +35,7 @@ BANZHAF = 1
 KERNEL_AUTO = 0
 KERNEL_GENERIC = 1
 KERNEL_SPECIALISED = 2
-KERNEL_QUADS = 16          # flag: merged sibling-pair tables in the specialised gather
+KERNEL_PAIRS = 16          # flag: one table per sibling pair in the specialised gather (no quads)
 
 MAX_DEPTH = 8
 SERVE_ONE_PER_LAUNCH = 1

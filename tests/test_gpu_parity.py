@@ -34,16 +34,16 @@ def _cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
 
 
-KERNELS = ["generic", "auto", "quads"]
+KERNELS = ["generic", "auto", "pairs"]
 
 
 def _kernel(wdf, name):
     return {"generic": wdf.KERNEL_GENERIC, "auto": wdf.KERNEL_AUTO,
-            "quads": wdf.KERNEL_AUTO | wdf.KERNEL_QUADS}[name]
+            "pairs": wdf.KERNEL_AUTO | wdf.KERNEL_PAIRS}[name]
 
 
 def _load(wdf, ctx, ens, kname):
-    """Load a model; with kname "auto" or "quads" the specialised kernels must be the ones in use."""
+    """Load a model; with kname "auto" or "pairs" the specialised kernels must be the ones in use."""
     model = wdf.Model(ctx, ens, _kernel(wdf, kname))
     assert model.specialised == (kname != "generic"), f"kernel choice {kname}: specialised={model.specialised}"
     return model

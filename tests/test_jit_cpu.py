@@ -32,27 +32,27 @@ def _explain_body(src):
 @pytest.mark.parametrize("quads", [False, True])
 def test_specialised_source_compiles(wdf, which, quads):
     ens = synth.WORKLOADS["small"].ensemble() if which == "small" else _edge()
-    kernel = wdf.KERNEL_SPECIALISED | (wdf.KERNEL_QUADS if quads else 0)
+    kernel = wdf.KERNEL_SPECIALISED | (0 if quads else wdf.KERNEL_PAIRS)
     src = wdf.specialised_source(ens, compile=True, kernel=kernel)
     assert "wdf_hist_spec" in src and "wdf_explain_spec" in src
 
 
 def test_gather_counts_match_the_layout(wdf):
-    """10 complete depth-4 trees: 8 pair groups of depth 4 per tree.  Pairs read
-    one value per (group, first-occurrence position); a quad reads one per
-    first-occurrence position of its two pairs, shared prefix positions once."""
+    """10 complete depth-4 trees: 8 pair groups of depth 4 per tree.  Pairs add
+    one value per (group, first-occurrence position); a quad adds one per
+    first-occurrence position of its two pairs, shared prefix positions once.
+    Each 16-byte read returns four values of an entry: one read per pair table
+    (4 values), two per quad table (5 values)."""
     ens = synth.WORKLOADS["small"].ensemble()
-    pairs = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED))
-    quads = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED | wdf.KERNEL_QUADS))
-    n_pair_reads = len(re.findall(r"\+= t\[", pairs))
-    n_quad_reads = len(re.findall(r"\+= t\[", quads))
-    # upper bounds: every position first
-    assert n_pair_reads <= 10 * 8 * 4
-    assert n_quad_reads <= 10 * 4 * 5
-    assert n_quad_reads < n_pair_reads
+    pairs = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED | wdf.KERNEL_PAIRS))
+    quads = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED))
+    pair_adds, quad_adds = len(re.findall(r"\+= a\.", pairs)), len(re.findall(r"\+= a\.", quads))
+    pair_reads, quad_reads = pairs.count("vf4 a = t["), quads.count("vf4 a = t[")
+    assert pair_adds <= 10 * 8 * 4 and quad_adds <= 10 * 4 * 5
+    assert quad_adds < pair_adds
+    assert 0 < pair_reads <= 10 * 8 and 0 < quad_reads <= 10 * 4 * 2  # planes without a first position are skipped
     # with raw-split patterns no pattern is ever flipped in the gather
     assert "^ 1u" not in pairs and "^ 1u" not in quads
     # every feature of the model is written to phi
     for f in range(ens.n_features):
         assert f"phi[{f} * ldphi + row]" in pairs
-
