@@ -42,7 +42,7 @@ struct JitPlan {
   int nt_hist = 512, nt_explain = 512;
   int explain_bpc = 1;           // explain blocks per CU sharing the LDS (512 / bpc threads each)
   int hist_cap = 32768;         // uint32 counters per histogram chunk (LDS)
-  int stage_floats_max = 12288; // table floats per explain stage (LDS, double-buffered)
+  int stage_floats_max = 40960; // table floats per explain stage (LDS, double-buffered; capped by what fits)
   int stage_floats = 12288;     // the same after room for the thresholds
   std::vector<float> thr_pad;   // used features' thresholds, NaN-padded to powers of two
   std::vector<int32_t> thr_pad_off, thr_steps;  // per feature: offset in thr_pad, search steps

@@ -410,19 +410,21 @@ struct CountGen {
       return std::string(tag) + std::to_string(id) + "_" + std::to_string(r) + (h ? "h" : "l");
     };
     if (level < 6) {
+      // one three-input op per half: acc & (S ^ E) (truth table 0x60) for the
+      // left child, acc & ~(S ^ E) (0x90) for the right child
       const std::string E = "E" + std::to_string(level);
-      const std::string xl = "xl" + std::to_string(id), xh = "xh" + std::to_string(id);
-      o << "const u32 " << xl << " = " << sl << " ^ " << E << ", " << xh << " = " << sh << " ^ " << E << ";\n";
       for (size_t r = 0; r < acc.size(); ++r) {
         if (need_l) {
           left.push_back({var("L", r, 0), var("L", r, 1)});
-          o << "const u32 " << left.back().lo << " = " << acc[r].lo << " & " << xl << ", " << left.back().hi << " = "
-            << acc[r].hi << " & " << xh << ";\n";
+          o << "const u32 " << left.back().lo << " = __builtin_amdgcn_bitop3_b32(" << acc[r].lo << ", " << sl << ", " << E
+            << ", 0x60), " << left.back().hi << " = __builtin_amdgcn_bitop3_b32(" << acc[r].hi << ", " << sh << ", "
+            << E << ", 0x60);\n";
         }
         if (need_r) {
           right.push_back({var("R", r, 0), var("R", r, 1)});
-          o << "const u32 " << right.back().lo << " = " << acc[r].lo << " & ~" << xl << ", " << right.back().hi
-            << " = " << acc[r].hi << " & ~" << xh << ";\n";
+          o << "const u32 " << right.back().lo << " = __builtin_amdgcn_bitop3_b32(" << acc[r].lo << ", " << sl << ", "
+            << E << ", 0x90), " << right.back().hi << " = __builtin_amdgcn_bitop3_b32(" << acc[r].hi << ", " << sh
+            << ", " << E << ", 0x90);\n";
         }
       }
     } else {
