@@ -154,8 +154,34 @@ int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float 
                 void *hip_stream);
 
 /* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
- * f(c) - base).  For a path-dependent summary: the cover-weighted mean. */
+ * f(c) - base).  For a path-dependent summary: the cover-weighted mean.  After
+ * a refresh (below) the value is read from the device: synchronise the
+ * refresh's stream first. */
 int wdf_base_value(const wdf_bg *bg, double *out);
+
+/* Recompute a background summary in place from new background rows: the same
+ * count m as at load, device pointer B [F][ldb >= m], column-major.  The same
+ * steps as wdf_background_load (threshold ranks, exact histograms, MFMA
+ * contraction, tables, base value; Section 7 steps (d)-(f)), enqueued on
+ * hip_stream as kernel launches only: no allocation after the first call (which
+ * allocates the summary's private workspace), no host copy, no
+ * synchronisation, so the call can be captured into a HIP graph.  The caller
+ * keeps B alive until the stream has run the work, and does not run explains
+ * of this summary concurrently with a refresh.
+ * Errors: INVALID_ARG (NULL, ldb < m, path-dependent summary), OOM, DEVICE. */
+int wdf_background_refresh(wdf_bg *bg, const float *B, int64_t ldb, void *hip_stream);
+
+/* A whole step recorded once into a HIP graph and replayed: the refresh of bg
+ * from B (skipped when B is NULL) followed by wdf_explain of X into phi
+ * (skipped when n == 0).  All pointers and sizes are fixed at creation; the
+ * caller changes the contents of B and X between launches and keeps every
+ * buffer alive while the graph exists.  Launches on one summary must not
+ * overlap.  Errors: INVALID_ARG, OOM, DEVICE. */
+typedef struct wdf_graph wdf_graph;
+int wdf_graph_create(wdf_bg *bg, const float *B, int64_t ldb, const float *X, int64_t n, int64_t ldx, float *phi,
+                     int64_t ldphi, wdf_graph **out);
+int wdf_graph_launch(wdf_graph *g, void *hip_stream);
+void wdf_graph_destroy(wdf_graph *g);
 
 /* ---- debug / parity (not on the hot path) ------------------------------- */
 

@@ -451,7 +451,43 @@ extern "C" int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32
 // (torch's default stream is the null stream).
 static hipStream_t pick_stream(wdf_ctx *, void *s) { return (hipStream_t)s; }
 
-// Columns, MFMA products per class, expansion into the gather tables, base value.
+// Table storage of a summary, zeroed once (the padding between tables is never
+// written again).
+static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
+  int rc;
+  if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(M->tab_size, 1) * sizeof(float)))) return rc;
+  HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));
+  if (M->jit) {
+    if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->jp.xtab_size, 1) * sizeof(float)))) return rc;
+    HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
+  }
+  return WDF_OK;
+}
+
+// Columns, MFMA products per class, expansion into the gather tables (and the
+// explain tables), base value into *base: kernel launches only.
+static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
+                            double *H, double *S, double *base, hipStream_t s) {
+  const int64_t G = (int64_t)M->groups.size();
+  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
+                         M->d_hclass_off.as<int64_t>(), H, s));
+  for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
+    const ClassInfo &c = M->cls[dp];
+    if (c.ncols == 0) continue;
+    const int K = 1 << dp, R = dp * K;
+    HIP_TRY(launch_gemm_f64(M->d_coef[bg->values][dp].as<double>(), H + c.h_off, S + c.s_off, R, K, c.ncols, s));
+  }
+  HIP_TRY(launch_expand(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_sclass_off.as<int64_t>(), S,
+                        bg->d_tab.as<float>(), nullptr, s));
+  if (M->jit)  // explain tables of the specialised kernel
+    HIP_TRY(launch_xtab(M->jp.d_xunits.as<XUnit>(), (int64_t)M->jp.xunits.size(), bg->d_tab.as<float>(),
+                        bg->d_xtab.as<float>(), s));
+  HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
+  return WDF_OK;
+}
+
+// Summary of a new background: tables allocated, contraction with the model's
+// shared workspace, base value copied to the host, stream synchronised.
 static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
                     hipStream_t s) {
   DevBuf &H = M->ws_H, &S = M->ws_S, &base = M->ws_base;
@@ -459,28 +495,9 @@ static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double
   if ((rc = ws_reserve(H, (size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
   if ((rc = ws_reserve(S, (size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
   if ((rc = ws_reserve(base, sizeof(double)))) return rc;
-  if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(M->tab_size, 1) * sizeof(float)))) return rc;
-  const int64_t G = (int64_t)M->groups.size();
-  HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));  // padding between tables
-  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
-                         M->d_hclass_off.as<int64_t>(), H.as<double>(), s));
-  for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
-    const ClassInfo &c = M->cls[dp];
-    if (c.ncols == 0) continue;
-    const int K = 1 << dp, R = dp * K;
-    HIP_TRY(launch_gemm_f64(M->d_coef[bg->values][dp].as<double>(), H.as<double>() + c.h_off,
-                            S.as<double>() + c.s_off, R, K, c.ncols, s));
-  }
-  HIP_TRY(launch_expand(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_sclass_off.as<int64_t>(),
-                        S.as<double>(), bg->d_tab.as<float>(), nullptr, s));
-  if (M->jit) {  // explain tables of the specialised kernel: quads merged from pairs
-    if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->jp.xtab_size, 1) * sizeof(float)))) return rc;
-    HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
-    HIP_TRY(launch_xtab(M->jp.d_xunits.as<XUnit>(), (int64_t)M->jp.xunits.size(), bg->d_tab.as<float>(),
-                        bg->d_xtab.as<float>(), s));
-  }
-  HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0,
-                      base.as<double>(), s));
+  if ((rc = alloc_tables(M, bg, s))) return rc;
+  if ((rc = enqueue_contract(M, bg, hist, freq, scale, H.as<double>(), S.as<double>(), base.as<double>(), s)))
+    return rc;
   HIP_TRY(hipMemcpyAsync(&bg->base, base.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return WDF_OK;
@@ -516,7 +533,8 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(uint32_t)))) return rc;
   HIP_TRY(hipMemsetAsync(bg->d_hist.ptr, 0, bg->d_hist.bytes, s));
   if (M->jit) {
-    if ((rc = jit_hist(M, Bd, m, ldb, bg->d_hist.as<uint32_t>(), s))) return rc;
+    if ((rc = ws_reserve(M->ws_codes, (size_t)M->jp.words * (size_t)m * sizeof(uint32_t)))) return rc;
+    if ((rc = jit_hist(M, Bd, m, ldb, bg->d_hist.as<uint32_t>(), M->ws_codes.as<uint32_t>(), s))) return rc;
   } else {
     HIP_TRY(launch_hist_generic(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(), Bd,
                                 m, ldb, bg->d_hist.as<uint32_t>(), s));
@@ -524,6 +542,110 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   if ((rc = contract(M, bg.get(), bg->d_hist.as<uint32_t>(), nullptr, 1.0 / (double)m, s))) return rc;
   *out = bg.release();
   return WDF_OK;
+}
+
+// Private workspace of in-place refreshes.
+static int ensure_refresh_workspace(wdf_bg *bg) {
+  wdf_model *M = bg->model;
+  int rc;
+  if (M->jit && !bg->own_codes.ptr &&
+      (rc = bg->own_codes.alloc((size_t)M->jp.words * (size_t)bg->m * sizeof(uint32_t))))
+    return rc;
+  if (!bg->own_H.ptr && (rc = bg->own_H.alloc((size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
+  if (!bg->own_S.ptr && (rc = bg->own_S.alloc((size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
+  if (!bg->d_base.ptr && (rc = bg->d_base.alloc(sizeof(double)))) return rc;
+  return WDF_OK;
+}
+
+// The launches of a refresh: histograms cleared by a kernel, recounted,
+// contracted; nothing else.
+static int enqueue_refresh(wdf_bg *bg, const float *B, int64_t ldb, hipStream_t s) {
+  wdf_model *M = bg->model;
+  const int64_t m = bg->m;
+  int rc;
+  HIP_TRY(launch_fill_u32(bg->d_hist.as<uint32_t>(), std::max<int64_t>(M->hist_size, 1), 0u, s));
+  if (M->jit) {
+    if ((rc = jit_hist(M, B, m, ldb, bg->d_hist.as<uint32_t>(), bg->own_codes.as<uint32_t>(), s))) return rc;
+  } else {
+    HIP_TRY(launch_hist_generic(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(), B, m,
+                                ldb, bg->d_hist.as<uint32_t>(), s));
+  }
+  return enqueue_contract(M, bg, bg->d_hist.as<uint32_t>(), nullptr, 1.0 / (double)m, bg->own_H.as<double>(),
+                          bg->own_S.as<double>(), bg->d_base.as<double>(), s);
+}
+
+static int check_refresh(const wdf_bg *bg, const float *B, int64_t ldb, const char *who) {
+  if (!bg || !B) return set_error(WDF_E_INVALID_ARG, "%s: NULL argument", who);
+  if (bg->pathdep) return set_error(WDF_E_INVALID_ARG, "%s: a path-dependent summary has no background", who);
+  if (ldb < bg->m) return set_error(WDF_E_INVALID_ARG, "%s: need ldb >= m", who);
+  return WDF_OK;
+}
+
+extern "C" int wdf_background_refresh(wdf_bg *bg, const float *B, int64_t ldb, void *hip_stream) {
+  int rc;
+  if ((rc = check_refresh(bg, B, ldb, "wdf_background_refresh"))) return rc;
+  HIP_TRY(hipSetDevice(bg->device));
+  if ((rc = ensure_refresh_workspace(bg))) return rc;
+  if ((rc = enqueue_refresh(bg, B, ldb, pick_stream(bg->model->ctx, hip_stream)))) return rc;
+  bg->base_on_device = true;
+  return WDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs: refresh + explain recorded once, replayed
+// ---------------------------------------------------------------------------
+
+extern "C" int wdf_graph_create(wdf_bg *bg, const float *B, int64_t ldb, const float *X, int64_t n, int64_t ldx,
+                                float *phi, int64_t ldphi, wdf_graph **out) {
+  if (!bg || !out) return set_error(WDF_E_INVALID_ARG, "wdf_graph_create: NULL argument");
+  *out = nullptr;
+  int rc;
+  if (B && (rc = check_refresh(bg, B, ldb, "wdf_graph_create"))) return rc;
+  if (n < 0 || (n > 0 && (!X || !phi || ldx < n || ldphi < n)))
+    return set_error(WDF_E_INVALID_ARG, "wdf_graph_create: need X, phi and 0 <= n <= ldx, ldphi");
+  if (!B && n == 0) return set_error(WDF_E_INVALID_ARG, "wdf_graph_create: nothing to record");
+  HIP_TRY(hipSetDevice(bg->device));
+  if (B && (rc = ensure_refresh_workspace(bg))) return rc;
+  std::unique_ptr<wdf_graph> g(new (std::nothrow) wdf_graph());
+  if (!g) return set_error(WDF_E_OOM, "wdf_graph_create: out of host memory");
+  g->bg = bg;
+  g->device = bg->device;
+  HIP_TRY(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+  auto fail = [&](int code) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipStreamDestroy(g->stream);
+    return code;
+  };
+  hipError_t e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail(hip_error(e, "hipStreamBeginCapture"));
+  rc = WDF_OK;
+  if (B) rc = enqueue_refresh(bg, B, ldb, g->stream);
+  if (!rc && n > 0) rc = wdf_explain(bg, X, n, ldx, phi, ldphi, g->stream);
+  e = hipStreamEndCapture(g->stream, &g->graph);
+  if (rc) return fail(rc);
+  if (e != hipSuccess) return fail(hip_error(e, "hipStreamEndCapture"));
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(hip_error(e, "hipGraphInstantiate"));
+  if (B) bg->base_on_device = true;  // the base value is read from the device from now on
+  *out = g.release();
+  return WDF_OK;
+}
+
+extern "C" int wdf_graph_launch(wdf_graph *g, void *hip_stream) {
+  if (!g) return set_error(WDF_E_INVALID_ARG, "wdf_graph_launch: NULL graph");
+  HIP_TRY(hipSetDevice(g->device));
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  return WDF_OK;
+}
+
+extern "C" void wdf_graph_destroy(wdf_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
 }
 
 extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_bg **out) {
@@ -559,6 +681,11 @@ extern "C" void wdf_bg_destroy(wdf_bg *bg) {
 
 extern "C" int wdf_base_value(const wdf_bg *bg, double *out) {
   if (!bg || !out) return set_error(WDF_E_INVALID_ARG, "wdf_base_value: NULL argument");
+  if (bg->base_on_device) {  // refreshed: the caller has synchronised the refresh's stream
+    HIP_TRY(hipSetDevice(bg->device));
+    HIP_TRY(hipMemcpy(out, bg->d_base.ptr, sizeof(double), hipMemcpyDeviceToHost));
+    return WDF_OK;
+  }
   *out = bg->base;
   return WDF_OK;
 }

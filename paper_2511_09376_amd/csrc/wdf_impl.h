@@ -123,6 +123,18 @@ struct wdf_bg {
   wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)
   wdf::DevBuf d_tab;    // float gather tables
   wdf::DevBuf d_xtab;   // explain tables of the specialised kernel (quads merged)
+  // private workspace of in-place refreshes (allocated by the first one):
+  // threshold ranks, contraction columns and products, the base value
+  wdf::DevBuf own_codes, own_H, own_S, d_base;
+  bool base_on_device = false;  // a refresh wrote the base value to d_base
+};
+
+struct wdf_graph {
+  wdf_bg *bg = nullptr;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace wdf {
@@ -130,7 +142,8 @@ namespace wdf {
 int jit_build(wdf_model *M);
 int jit_source(wdf_model *M, bool do_compile, std::string &src);
 int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
-int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s);
+// background histograms; `codes` holds P.words * m words of threshold ranks
+int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, uint32_t *codes, hipStream_t s);
 // Grow a workspace buffer to at least `bytes` (contents are not kept).
 int ws_reserve(DevBuf &buf, size_t bytes);
 int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s);

@@ -774,13 +774,10 @@ int jit_build(wdf_model *M) {
   return WDF_OK;
 }
 
-int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, hipStream_t s) {
+int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, uint32_t *codes, hipStream_t s) {
   const JitPlan &P = M->jp;
-  DevBuf &codes = M->ws_codes;  // the caller holds the model's workspace lock
-  int rc;
-  if ((rc = ws_reserve(codes, (size_t)P.words * (size_t)m * sizeof(uint32_t)))) return rc;
   hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr_pad.as<float>(), P.d_pad_meta.as<int2>(), P.wide,
-                                 P.words, codes.as<uint32_t>(), m, s);
+                                 P.words, codes, m, s);
   if (e != hipSuccess) return hip_error(e, "quantize");
   // one block per CU at a time (the LDS histogram); a whole number of rounds
   // over the CUs, split evenly between the chunks
@@ -790,7 +787,7 @@ int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *his
   blocks = std::min<int64_t>(blocks, (ntiles + P.nt_hist / 64 - 1) / (P.nt_hist / 64));
   int64_t tiles_per_block = (ntiles + blocks - 1) / blocks;
   blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
-  const uint32_t *cp = codes.as<uint32_t>();
+  const uint32_t *cp = codes;
   const uint32_t *perm = P.d_perm.as<uint32_t>();
   int64_t ldc = m;
   int live = 1;

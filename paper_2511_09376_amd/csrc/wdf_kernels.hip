@@ -414,6 +414,19 @@ __global__ __launch_bounds__(256) void k_xtab(const XUnit *__restrict__ units, c
   }
 }
 
+// p[0, n) = v: a kernel rather than a memset node, so that captured graphs
+// hold kernels only
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_xtab(const XUnit *units, int64_t n_units, const float *tab, float *xtab, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_xtab, dim3((unsigned)n_units), dim3(256), 0, s, units, tab, xtab);

@@ -93,7 +93,8 @@ def _finalizing() -> bool:
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
-    "wdf_base_value", "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
+    "wdf_base_value", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
+    "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
     "wdf_debug_specialised_source", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
@@ -120,6 +121,10 @@ def lib():
         L.wdf_bg_destroy.argtypes = [P]
         L.wdf_explain.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_base_value.argtypes = [P, C.POINTER(C.c_double)]
+        L.wdf_background_refresh.argtypes = [P, P, I64, P]
+        L.wdf_graph_create.argtypes = [P, P, I64, P, I64, I64, P, I64, C.POINTER(P)]
+        L.wdf_graph_launch.argtypes = [P, P]
+        L.wdf_graph_destroy.argtypes = [P]
         L.wdf_debug_patterns.argtypes = [P, P, I64, I64, P, P]
         L.wdf_debug_histograms.argtypes = [P, P, I64]
         L.wdf_debug_histograms.restype = I64
@@ -303,6 +308,14 @@ class Background:
                                  _stream_handle(stream)))
         return out
 
+    def refresh(self, B, stream=None):
+        """Recompute the summary in place from new background rows B (CUDA
+        tensor [n_features, m], the same m); kernel launches only."""
+        B = _colmajor_tensor(B, self.model.n_features, "B")
+        if self.m and B.shape[1] != self.m:
+            raise ValueError(f"refresh needs {self.m} background rows, got {B.shape[1]}")
+        _check(lib().wdf_background_refresh(self.h, C.c_void_p(B.data_ptr()), B.stride(0), _stream_handle(stream)))
+
     def histograms(self) -> np.ndarray:
         n = _check(lib().wdf_debug_histograms(self.h, None, 0))
         out = np.empty(n, np.uint32)
@@ -318,6 +331,49 @@ class Background:
     def close(self):
         if getattr(self, "h", None):
             lib().wdf_bg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A refresh of `bg` from B (optional) plus an explain of X into phi,
+    recorded once into a HIP graph; launch() replays it.  The tensors are
+    captured by address: keep them alive and change their contents only."""
+
+    def __init__(self, bg: Background, X=None, phi=None, B=None):
+        F = bg.model.n_features
+        self.bg = bg
+        self._keep = (X, phi, B)
+        Bp, ldb = None, 0
+        if B is not None:
+            B = _colmajor_tensor(B, F, "B")
+            if B.shape[1] != bg.m:
+                raise ValueError(f"graph refresh needs {bg.m} background rows, got {B.shape[1]}")
+            Bp, ldb = C.c_void_p(B.data_ptr()), B.stride(0)
+        Xp, Pp, n, ldx, ldp = None, None, 0, 0, 0
+        if X is not None:
+            X = _colmajor_tensor(X, F, "X")
+            phi = _colmajor_tensor(phi, F, "phi")
+            n = X.shape[1]
+            Xp, Pp, ldx, ldp = C.c_void_p(X.data_ptr()), C.c_void_p(phi.data_ptr()), X.stride(0), phi.stride(0)
+        h = C.c_void_p()
+        _check(lib().wdf_graph_create(bg.h, Bp, ldb, Xp, n, ldx, Pp, ldp, C.byref(h)))
+        self.h = h
+        _track(self)
+
+    def launch(self, stream=None):
+        _check(lib().wdf_graph_launch(self.h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().wdf_graph_destroy(self.h)
             self.h = None
 
     def __del__(self):
