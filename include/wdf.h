@@ -203,6 +203,29 @@ int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap);
  * WDF_KERNEL_PAIRS matters here).  For tools and tests; needs no GPU. */
 int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int compile, char *out, int64_t cap);
 
+/* ---- autotuning --------------------------------------------------------- */
+
+/* Launch configurations measured by wdf_model_autotune (times in ms, -1 when
+ * not measured). */
+typedef struct {
+  int quads;                  /* chosen explain gather: 1 quad tables, 0 pair tables */
+  int hist_rounds;            /* chosen histogram grid: blocks per CU over the launch */
+  float explain_ms[2];        /* explain time with [0] pair tables, [1] quad tables */
+  float hist_ms[9];           /* histogram time with hist_rounds = index (1..8) */
+} wdf_tuning;
+
+/* Measure the model's specialised kernels on the caller's data and keep the
+ * fastest configuration for later calls: the explain gather (pair or quad
+ * tables, a compile-time choice: each variant is generated and compiled once
+ * and cached) and the histogram grid (a launch-time choice).  B [F][ldb] (m
+ * rows) and X [F][ldx] (n rows) are device pointers; a sample of a few hundred
+ * thousand rows is enough.  Runs and synchronises on hip_stream.  No summary
+ * of the model may exist during the call (summaries hold tables laid out for
+ * the gather in use).  Errors: INVALID_ARG (NULL, sizes, summaries exist),
+ * UNSUPPORTED (the model runs the generic kernels), COMPILE, OOM, DEVICE. */
+int wdf_model_autotune(wdf_model *model, const float *B, int64_t m, int64_t ldb, const float *X, int64_t n,
+                       int64_t ldx, void *hip_stream, wdf_tuning *out);
+
 /* ---- serving: continuous batching of explain requests ------------------- */
 
 typedef struct wdf_server wdf_server;

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwdf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["wdf_host.cpp", "wdf_jit.cpp", "wdf_serve.cpp", "wdf_kernels.hip"]
+SOURCES = ["wdf_host.cpp", "wdf_jit.cpp", "wdf_serve.cpp", "wdf_tune.cpp", "wdf_kernels.hip"]
 # Packed FP32 instructions are kept out of every device build.
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -45,12 +45,6 @@ int hip_error(hipError_t e, const char *what) {
 
 extern "C" const char *wdf_last_error(void) { return g_err.c_str(); }
 
-#define HIP_TRY(expr)                                   \
-  do {                                                  \
-    hipError_t e_ = (expr);                             \
-    if (e_ != hipSuccess) return hip_error(e_, #expr);  \
-  } while (0)
-
 // ---------------------------------------------------------------------------
 // Device buffers
 // ---------------------------------------------------------------------------
@@ -540,6 +534,7 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
                                 m, ldb, bg->d_hist.as<uint32_t>(), s));
   }
   if ((rc = contract(M, bg.get(), bg->d_hist.as<uint32_t>(), nullptr, 1.0 / (double)m, s))) return rc;
+  ++M->n_bg;
   *out = bg.release();
   return WDF_OK;
 }
@@ -669,6 +664,7 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   HIP_TRY(launch_pd_freq(M->d_groups.as<Group>(), (int64_t)M->groups.size(), M->d_ratio.as<double>(),
                          bg->d_hist.as<double>(), s));
   if ((rc = contract(M, bg.get(), nullptr, bg->d_hist.as<double>(), 1.0, s))) return rc;
+  ++M->n_bg;
   *out = bg.release();
   return WDF_OK;
 }
@@ -676,6 +672,7 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
 extern "C" void wdf_bg_destroy(wdf_bg *bg) {
   if (!bg) return;
   (void)hipSetDevice(bg->device);
+  --bg->model->n_bg;
   delete bg;
 }
 

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <map>
 #include <memory>
 #include <mutex>
@@ -15,6 +17,13 @@ namespace wdf {
 
 int set_error(int code, const char *fmt, ...);
 int hip_error(hipError_t e, const char *what);
+
+// return the library error for a failed HIP call
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_error(e_, #expr);  \
+  } while (0)
 
 struct DevBuf {
   void *ptr = nullptr;
@@ -111,6 +120,8 @@ struct wdf_model {
   // one model
   std::mutex ws_mu;
   wdf::DevBuf ws_codes, ws_H, ws_S, ws_base;
+
+  std::atomic<int> n_bg{0};  // live background summaries (their tables follow the current plan)
 };
 
 struct wdf_bg {

@@ -1,0 +1,111 @@
+// Autotuner of the model-specialised kernels: every candidate configuration
+// is run on the caller's data and timed with HIP events; the fastest is kept.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+
+#include "wdf.h"
+#include "wdf_dev.h"
+#include "wdf_impl.h"
+#include "wdf_internal.h"
+
+using namespace wdf;
+
+namespace {
+
+struct Events {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Events() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// average duration of `reps` runs of f after one warm-up run; -1 on error
+template <class Fn>
+float time_runs(hipStream_t s, int reps, Fn f, int &rc) {
+  Events ev;
+  if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) {
+    rc = set_error(WDF_E_DEVICE, "autotune: hipEventCreate failed");
+    return -1.f;
+  }
+  if ((rc = f())) return -1.f;
+  if (hipEventRecord(ev.a, s) != hipSuccess) return rc = set_error(WDF_E_DEVICE, "autotune: event"), -1.f;
+  for (int r = 0; r < reps; ++r)
+    if ((rc = f())) return -1.f;
+  if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess)
+    return rc = set_error(WDF_E_DEVICE, "autotune: event"), -1.f;
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, ev.a, ev.b);
+  return ms / (float)reps;
+}
+
+}  // namespace
+
+extern "C" int wdf_model_autotune(wdf_model *M, const float *B, int64_t m, int64_t ldb, const float *X, int64_t n,
+                                  int64_t ldx, void *hip_stream, wdf_tuning *out) {
+  if (!M || !B || !X || !out) return set_error(WDF_E_INVALID_ARG, "wdf_model_autotune: NULL argument");
+  if (m < 1 || ldb < m || n < 1 || ldx < n) return set_error(WDF_E_INVALID_ARG, "wdf_model_autotune: bad sizes");
+  if (!M->jit) return set_error(WDF_E_UNSUPPORTED, "wdf_model_autotune: the model runs the generic kernels");
+  if (M->n_bg.load() != 0)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_autotune: %d background summaries of this model exist",
+                     M->n_bg.load());
+  HIP_TRY(hipSetDevice(M->ctx->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  *out = wdf_tuning{};
+  for (float &t : out->explain_ms) t = -1.f;
+  for (float &t : out->hist_ms) t = -1.f;
+  const int reps = 3;
+  int rc = WDF_OK;
+
+  // histogram grid: a launch-time choice, timed on one histogram buffer
+  {
+    DevBuf hist, codes;
+    if ((rc = hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(uint32_t)))) return rc;
+    if ((rc = codes.alloc((size_t)M->jp.words * (size_t)m * sizeof(uint32_t)))) return rc;
+    const int keep = M->jp.hist_rounds;
+    int best = keep;
+    float best_ms = -1.f;
+    for (int r : {1, 2, 3, 4, 6, 8}) {
+      M->jp.hist_rounds = r;
+      const float ms = time_runs(s, reps, [&] {
+        HIP_TRY(launch_fill_u32(hist.as<uint32_t>(), std::max<int64_t>(M->hist_size, 1), 0u, s));
+        return jit_hist(M, B, m, ldb, hist.as<uint32_t>(), codes.as<uint32_t>(), s);
+      }, rc);
+      if (rc) {
+        M->jp.hist_rounds = keep;
+        return rc;
+      }
+      out->hist_ms[r] = ms;
+      if (best_ms < 0.f || ms < best_ms) best_ms = ms, best = r;
+    }
+    M->jp.hist_rounds = best;
+    out->hist_rounds = best;
+  }
+
+  // explain gather: a compile-time choice; each variant gets a summary of B
+  DevBuf phi;
+  if ((rc = phi.alloc((size_t)M->n_features * (size_t)n * sizeof(float)))) return rc;
+  const bool keep_quads = M->jp.quads;
+  for (int q : {0, 1}) {
+    M->jp.quads = q != 0;
+    if ((rc = jit_build(M))) break;
+    wdf_bg *bg = nullptr;
+    if ((rc = wdf_background_load(M, B, m, ldb, 1, WDF_SHAPLEY, s, &bg))) break;
+    const float ms = time_runs(s, reps, [&] { return wdf_explain(bg, X, n, ldx, phi.as<float>(), n, s); }, rc);
+    wdf_bg_destroy(bg);
+    if (rc) break;
+    out->explain_ms[q] = ms;
+  }
+  if (rc) {  // back to the plan the model had (its module is cached)
+    M->jp.quads = keep_quads;
+    (void)jit_build(M);
+    return rc;
+  }
+  M->jp.quads = out->explain_ms[1] <= out->explain_ms[0];
+  out->quads = M->jp.quads ? 1 : 0;
+  if ((rc = jit_build(M))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  return WDF_OK;
+}

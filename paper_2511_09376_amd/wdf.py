@@ -90,12 +90,17 @@ def _finalizing() -> bool:
     return sys.is_finalizing()
 
 
+class Tuning(C.Structure):
+    _fields_ = [("quads", C.c_int), ("hist_rounds", C.c_int), ("explain_ms", C.c_float * 2),
+                ("hist_ms", C.c_float * 9)]
+
+
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
     "wdf_base_value", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
-    "wdf_debug_specialised_source", "wdf_server_create",
+    "wdf_debug_specialised_source", "wdf_model_autotune", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
 
@@ -132,6 +137,7 @@ def lib():
         L.wdf_debug_tables.restype = I64
         L.wdf_debug_specialised_source.argtypes = [P, I, I, P, I64]
         L.wdf_debug_specialised_source.restype = I64
+        L.wdf_model_autotune.argtypes = [P, P, I64, I64, P, I64, I64, P, C.POINTER(Tuning)]
         L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
         L.wdf_server_wait.argtypes = [P, C.c_uint64, I]
@@ -225,6 +231,20 @@ class Model:
     @property
     def specialised(self) -> bool:
         return bool(lib().wdf_model_specialised(self.h))
+
+    def autotune(self, B, X, stream=None) -> dict:
+        """Time the specialised kernels' configurations on device tensors B
+        [n_features, m] and X [n_features, n] and keep the fastest (no summary
+        of this model may exist).  Returns the measurements."""
+        B = _colmajor_tensor(B, self.n_features, "B")
+        X = _colmajor_tensor(X, self.n_features, "X")
+        t = Tuning()
+        _check(lib().wdf_model_autotune(self.h, C.c_void_p(B.data_ptr()), B.shape[1], B.stride(0),
+                                        C.c_void_p(X.data_ptr()), X.shape[1], X.stride(0), _stream_handle(stream),
+                                        C.byref(t)))
+        return {"gather": "quads" if t.quads else "pairs", "hist_rounds": int(t.hist_rounds),
+                "explain_ms": {"pairs": float(t.explain_ms[0]), "quads": float(t.explain_ms[1])},
+                "hist_ms": {str(r): float(t.hist_ms[r]) for r in range(1, 9) if t.hist_ms[r] >= 0}}
 
     def groups(self) -> dict:
         G = _check(lib().wdf_model_groups(self.h, None, None, None, None, None, None))
