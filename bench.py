@@ -60,6 +60,27 @@ def method_ops_per_row(ens) -> int:  # noqa: C901
     return int(total)
 
 
+def measured_traffic(wdf, ens, workload, gather):
+    """HBM bytes per explain launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), reported
+    only while the generated kernel source is the one the counters were
+    taken on; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"explain_{gather}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    flags = wdf.KERNEL_SPECIALISED | (wdf.KERNEL_PAIRS if gather == "pairs" else 0)
+    sha = hashlib.sha1(wdf.specialised_source(ens, kernel=flags).encode()).hexdigest()
+    if fields.get("source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(ens, X_rows, B, seconds_hint=20.0):
     """The FP64 oracle (depth-first walk form), unchanged, on a bounded sample:
     one consumer row per host core against a prefix of the background sized to
@@ -239,9 +260,12 @@ def main():
 
     ops_row = int(method_ops_per_row(ens))
     achieved = ops_row * n / (explain_ms * 1e-3)
+    gather = tuning["gather"] if tuning else ("quads" if model.specialised else None)
+    traffic = measured_traffic(wdf, ens, args.workload, gather) if gather else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                "kernel": "explain", "kernel_ms": explain_ms, "ops_per_row": ops_row}
+                "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+                "kernel": f"wdf_explain_{gather}" if gather else "k_explain_generic", "kernel_ms": explain_ms,
+                "ops_per_row": ops_row}
     base = bg.base_value
     out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

@@ -222,6 +222,9 @@ typedef long long i64;
 #define TS(t, w, sel, j1) do { u32 s_; asm("s_mov_b32 %1, " #j1 "\n\tv_sub_u32_sdwa %0, sext(%2), %1 src0_sel:" sel " src1_sel:DWORD" : "=v"(t), "=&s"(s_) : "v"(w)); } while (0)
 )";
 
+// the explain kernel is named by its gather, so that profiles tell the variants apart
+const char *explain_kernel_name(const JitPlan &P) { return P.quads ? "wdf_explain_quads" : "wdf_explain_pairs"; }
+
 struct TreeIndex {
   // per global node: group indices hanging off it, and the group range below it
   std::vector<int64_t> pair_of, single_l, single_r, gmin, gmax;
@@ -528,6 +531,7 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
   o << kPreamble;
   o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n"
+    << "#define EXPLAIN_NAME " << explain_kernel_name(P) << "\n"
     << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
   o << R"(
 __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float* dst, int n16) {
@@ -539,7 +543,7 @@ __device__ __forceinline__ void stage_copy(const float* __restrict__ src, float*
   }
 }
 // one row per lane, one tile of NT rows per block
-extern "C" __global__ __launch_bounds__(NT, 2) void wdf_explain_spec(const float* __restrict__ X, i64 ldx,
+extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __restrict__ X, i64 ldx,
                                                                      const float* __restrict__ tab,
                                                                      const float* __restrict__ thr,
                                                                      float* __restrict__ phi, i64 ldphi, i64 n, int live) {
@@ -737,8 +741,8 @@ int jit_build(wdf_model *M) {
     if (e != hipSuccess) return hip_error(e, "hipModuleLoadData");
     if ((e = hipModuleGetFunction(&m->hist, m->mod, "wdf_hist_spec")) != hipSuccess)
       return hip_error(e, "hipModuleGetFunction(wdf_hist_spec)");
-    if ((e = hipModuleGetFunction(&m->explain, m->mod, "wdf_explain_spec")) != hipSuccess)
-      return hip_error(e, "hipModuleGetFunction(wdf_explain_spec)");
+    if ((e = hipModuleGetFunction(&m->explain, m->mod, explain_kernel_name(M->jp))) != hipSuccess)
+      return hip_error(e, "hipModuleGetFunction(explain)");
     std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
     M->ctx->jit_cache[src] = m;
     mod = m;

@@ -25,7 +25,7 @@ def _edge():
 
 
 def _explain_body(src):
-    return src[src.index("wdf_explain_spec"):]
+    return src[src.index("#define EXPLAIN_NAME"):]
 
 
 @pytest.mark.parametrize("which", ["small", "edge"])
@@ -34,7 +34,7 @@ def test_specialised_source_compiles(wdf, which, quads):
     ens = synth.WORKLOADS["small"].ensemble() if which == "small" else _edge()
     kernel = wdf.KERNEL_SPECIALISED | (0 if quads else wdf.KERNEL_PAIRS)
     src = wdf.specialised_source(ens, compile=True, kernel=kernel)
-    assert "wdf_hist_spec" in src and "wdf_explain_spec" in src
+    assert "wdf_hist_spec" in src and ("wdf_explain_quads" if quads else "wdf_explain_pairs") in src
 
 
 def test_gather_counts_match_the_layout(wdf):
