@@ -142,13 +142,14 @@ int make_plan(wdf_model *M) {
       P.thr_pad.push_back(i < K ? P.thr[(size_t)(P.thr_off[(size_t)f] + i)] : std::nanf(""));
   }
   while (P.thr_pad.size() % 4) P.thr_pad.push_back(std::nanf(""));
-  // LDS: thresholds (when they are few enough) plus two table stages within
-  // the 160 KB of a workgroup; more thresholds are searched in global memory
+  // LDS: two table stages fill the 160 KB of a workgroup; the thresholds
+  // borrow the stage buffers while the ranks are searched (more thresholds
+  // than the buffers hold are searched in global memory)
   const int64_t lds_floats = 160 * 1024 / 4;
-  P.thr_in_lds = P.thr_pad.size() <= 8192;
   P.nt_explain = 512 / P.explain_bpc;
-  const int64_t room = (lds_floats / P.explain_bpc - (P.thr_in_lds ? (int64_t)P.thr_pad.size() : 0)) / 2 / 4 * 4;
+  const int64_t room = lds_floats / P.explain_bpc / 2 / 4 * 4;
   P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
+  P.thr_in_lds = (int64_t)P.thr_pad.size() <= 2 * (int64_t)P.stage_floats;
   int max_table = 0;
   for (const Group &g : M->groups) max_table = std::max(max_table, 4 * ((g.depth + 3) / 4) << g.depth);
   if (P.stage_floats < max_table)
@@ -552,8 +553,25 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
 )";
+  const auto &S = P.explain_stages;
+  // unit of every group, and the explain-table span of a stage
+  std::vector<int64_t> unit_of(M->groups.size());
+  for (size_t u = 0; u + 1 < P.unit_g0.size(); ++u)
+    for (int64_t g = P.unit_g0[u]; g < P.unit_g0[u + 1]; ++g) unit_of[(size_t)g] = (int64_t)u;
+  auto unit_size = [&](int64_t u) { return xunit_floats(P.xunits[(size_t)u]); };
+  auto stage_span = [&](size_t s, int64_t &t0, int64_t &n16) {
+    const int64_t ua = unit_of[(size_t)S[s].first], ub = unit_of[(size_t)S[s].second - 1];
+    t0 = P.xunits[(size_t)ua].dst;
+    n16 = (P.xunits[(size_t)ub].dst + unit_size(ub) - t0) / 4;
+  };
+  int64_t t0, n16;
+  stage_span(0, t0, n16);
+  // thresholds in the second stage buffer when they fit there, so that the
+  // first stage loads during the rank search; else across both buffers
+  const bool thr_hi = P.thr_in_lds && (int64_t)P.thr_pad.size() <= P.stage_floats;
+  if (thr_hi) o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n";
   if (P.thr_in_lds)
-    o << "  __shared__ __attribute__((aligned(16))) float lthr[TF];\n"
+    o << "  float* lthr = lds + " << (thr_hi ? P.stage_floats : 0) << ";\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
   for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
 
@@ -597,21 +615,9 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   }
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
-  const auto &S = P.explain_stages;
-  // unit of every group, and the explain-table span of a stage
-  std::vector<int64_t> unit_of(M->groups.size());
-  for (size_t u = 0; u + 1 < P.unit_g0.size(); ++u)
-    for (int64_t g = P.unit_g0[u]; g < P.unit_g0[u + 1]; ++g) unit_of[(size_t)g] = (int64_t)u;
-  auto unit_size = [&](int64_t u) { return xunit_floats(P.xunits[(size_t)u]); };
-  auto stage_span = [&](size_t s, int64_t &t0, int64_t &n16) {
-    const int64_t ua = unit_of[(size_t)S[s].first], ub = unit_of[(size_t)S[s].second - 1];
-    t0 = P.xunits[(size_t)ua].dst;
-    n16 = (P.xunits[(size_t)ub].dst + unit_size(ub) - t0) / 4;
-  };
-  int64_t t0, n16;
-  stage_span(0, t0, n16);
-  o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n"
-    << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
+  if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
+  if (!thr_hi) o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n";
+  o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
   for (size_t s = 0; s < S.size(); ++s) {
     const int buf = (int)(s & 1);
     if (s + 1 < S.size()) {
