@@ -174,6 +174,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--values", default="shapley", choices=["shapley", "banzhaf"],
+                    help="value kind: Shapley (default) or Banzhaf values of the same game")
+    ap.add_argument("--pathdep", action="store_true",
+                    help="path-dependent values from node covers (no background: the summary depends on the model "
+                         "only, so a step is one explain)")
     ap.add_argument("--eager", action="store_true", help="launch the step's kernels directly instead of replaying HIP graphs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times (counter calibration)")
@@ -221,19 +226,35 @@ def main():
         tuning = model.autotune(Bd, Xd)        # on the workload itself: the choice transfers exactly
         print(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {tuning}", file=sys.stderr, flush=True)
     # the summary's storage is allocated once; a step then recomputes it in
-    # place from the (resident) background and explains every consumer row
-    bg = wdf.Background(model, Bd)
+    # place from the (resident) background and explains every consumer row.
+    # A path-dependent summary depends on the model only: it is built once and
+    # a step is one explain.
+    values = wdf.BANZHAF if args.values == "banzhaf" else wdf.SHAPLEY
+    summary_once_ms = None
+    if args.pathdep:
+        t0 = time.perf_counter()
+        bg = wdf.Background(model, values=values, pathdep=True)
+        torch.cuda.synchronize()
+        summary_once_ms = (time.perf_counter() - t0) * 1e3
+    else:
+        bg = wdf.Background(model, Bd, values=values)
     if args.eager:
         def summarise():
-            bg.refresh(Bd, stream=stream)
+            if not args.pathdep:
+                bg.refresh(Bd, stream=stream)
 
         def explain():
             bg.explain(Xd, out=phi, stream=stream)
     else:
-        g_bg = wdf.Graph(bg, B=Bd)             # refresh: ranks, histograms, contraction, tables
-        g_ex = wdf.Graph(bg, Xd, phi)          # one explain launch over all trees
-        summarise = lambda: g_bg.launch(stream)  # noqa: E731
-        explain = lambda: g_ex.launch(stream)    # noqa: E731
+        g_bg = None if args.pathdep else wdf.Graph(bg, B=Bd)  # ranks, histograms, contraction, tables
+        g_ex = wdf.Graph(bg, Xd, phi)                          # one explain launch over all trees
+
+        def summarise():
+            if g_bg is not None:
+                g_bg.launch(stream)
+
+        def explain():
+            g_ex.launch(stream)
 
     def step(ev=None):
         summarise()
@@ -273,16 +294,19 @@ def main():
            "config": {"workload": DESCRIPTIONS[args.workload], "n_consumers": int(n), "n_background": int(B.shape[1]),
                       "n_trees": ens.n_trees, "n_features": ens.n_features,
                       "kernel": "specialised" if model.specialised else "generic",
-                      "launch": "eager" if args.eager else "hip_graph"},
+                      "launch": "eager" if args.eager else "hip_graph",
+                      "values": args.values, "background": "path-dependent (covers)" if args.pathdep else "rows"},
            "roofline": roofline, "base_value": base, "tuning": tuning,
            "explain_rows_per_s": n / (explain_ms * 1e-3),
            "background_ms": ms_step - explain_ms}
+    if summary_once_ms is not None:
+        out["pathdep_summary_once_ms"] = summary_once_ms
     if not args.no_serve:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = serve_bench(wdf, ctx)
         sv = out["serving"]["loads"][0]["continuous_batching"]
         out["served_p50_ms"], out["served_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.pathdep and args.values == "shapley":
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ens, X[:, :64], B, args.cpu_seconds)
     print(json.dumps(out), flush=True)
