@@ -59,7 +59,9 @@ def lib():
         L.wo_wdnf_eval.restype = C.c_double
         L.wo_wdnf_values.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
         L.wo_wdnf_bruteforce.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
-        for fn in (L.wo_bg_fourrule, L.wo_bg_walk, L.wo_bg_bruteforce):
+        L.wo_wdnf_iv_values.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
+        L.wo_wdnf_iv_bruteforce.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
+        for fn in (L.wo_bg_fourrule, L.wo_bg_walk, L.wo_bg_bruteforce, L.wo_bg_iv_walk, L.wo_bg_iv_bruteforce):
             fn.argtypes = [P, P, I64, I64, P, I64, I64, C.c_int, P, I64, C.c_int]
         L.wo_map_patterns_to_cube.argtypes = [C.c_int, P, P, P, P]
         L.wo_map_patterns_to_cube.restype = I64
@@ -174,6 +176,29 @@ def bg_bruteforce(model, Cm, Bm, kind=SHAPLEY, threads=8):
     return _bg(lib().wo_bg_bruteforce, model, Cm, Bm, kind, threads)
 
 
+def _bg_iv(fn, model, Cm, Bm, kind, threads):
+    Cm, Bm = _colmajor(Cm), _colmajor(Bm)
+    n, m = Cm.shape[1], Bm.shape[1]
+    F = model.n_features
+    iv = np.zeros((F * F, n), np.float64)
+    rc = fn(model.ref, _ptr(Cm), n, n, _ptr(Bm), m, m, kind, _ptr(iv), n, threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle call failed ({rc})")
+    return iv.reshape(F, F, n)
+
+
+def bg_iv_walk(model, Cm, Bm, kind=SHAPLEY, threads=8):
+    """Background interaction values by the per-cube formulas (Table table_shap_iv,
+    Formula banzhaf_simplified_formula_interactions) over the walk's satisfiable
+    cubes; iv[i][j][n] in float64, diagonal 0."""
+    return _bg_iv(lib().wo_bg_iv_walk, model, Cm, Bm, kind, threads)
+
+
+def bg_iv_bruteforce(model, Cm, Bm, kind=SHAPLEY, threads=8):
+    """Interaction values from their definitions on the Background-SHAP game (F <= 20)."""
+    return _bg_iv(lib().wo_bg_iv_bruteforce, model, Cm, Bm, kind, threads)
+
+
 def _cubes(cubes):
     """cubes: list of (weight, [signed 1-based literals])."""
     w = np.array([c[0] for c in cubes], np.float64)
@@ -202,6 +227,23 @@ def wdnf_bruteforce(cubes, n_vars, kind=SHAPLEY) -> np.ndarray:
     out = np.empty(n_vars, np.float64)
     lib().wo_wdnf_bruteforce(n_vars, len(cubes), _ptr(w), _ptr(lits), ml, kind, _ptr(out))
     return out
+
+
+def wdnf_iv_values(cubes, n_vars, kind=SHAPLEY) -> np.ndarray:
+    """Interaction values of a WDNF by the per-cube formulas; [n_vars][n_vars]."""
+    w, lits, ml = _cubes(cubes)
+    out = np.empty(n_vars * n_vars, np.float64)
+    lib().wo_wdnf_iv_values(n_vars, len(cubes), _ptr(w), _ptr(lits), ml, kind, _ptr(out))
+    return out.reshape(n_vars, n_vars)
+
+
+def wdnf_iv_bruteforce(cubes, n_vars, kind=SHAPLEY) -> np.ndarray:
+    """Interaction values of a WDNF from their definitions over all assignments."""
+    w, lits, ml = _cubes(cubes)
+    out = np.empty(n_vars * n_vars, np.float64)
+    if lib().wo_wdnf_iv_bruteforce(n_vars, len(cubes), _ptr(w), _ptr(lits), ml, kind, _ptr(out)) != 0:
+        raise ValueError("wdnf_iv_bruteforce needs 2 <= n_vars <= 20")
+    return out.reshape(n_vars, n_vars)
 
 
 def map_patterns_to_cube(d: int):

@@ -30,6 +30,13 @@
  *   wo_woodelf_tables       Alg. 3 steps 2-3: M_{l,i}[p_c][p_b] from Alg. 2 and the
  *                           value function, s_{l,i} = w_l * M_{l,i} * f_l
  *   wo_pd_freq              Formula eq:path_dependent_estimation (Section 8)
+ *   wo_wdnf_iv_values       interaction values of a WDNF: Table table_shap_iv (Shapley)
+ *                           and Formula banzhaf_simplified_formula_interactions (Banzhaf)
+ *   wo_wdnf_iv_bruteforce   the same from the definitions (Def. shap_iv_def: phi_{j|i=1}
+ *                           - phi_{j|i=0}; Def. banzhaf_iv_def) over all assignments
+ *   wo_bg_iv_walk           Background interaction values: the depth-first walk with
+ *                           every satisfiable cube valued by the interaction formulas
+ *   wo_bg_iv_bruteforce     the same from the definitions on the Background-SHAP game
  *
  * Readings of the paper taken here (the paper is silent on them):
  *   - a missing (NaN) feature value follows the node's default direction;
@@ -215,6 +222,33 @@ static void credit_cube(int kind, double w, const int32_t *sp, int na, const int
     double c = w * cube_coef(kind, na, nb, 0);
     for (int i = 0; i < nb; ++i) phi[sm[i]] += c;
   }
+}
+
+/* Interaction value of the ordered pair (i, j), i != j, both literals of one
+ * cube with a positive and b negated distinct features (s = a + b):
+ * Table table_shap_iv for Shapley, Formula
+ * banzhaf_simplified_formula_interactions for Banzhaf.  pi, pj: 1 when the
+ * literal of i (j) is positive. */
+static double cube_iv_coef(int kind, int a, int b, int pi, int pj) {
+  int s = a + b;
+  if (kind == WO_BANZHAF) return (pi == pj ? 1.0 : -1.0) / ldexp(1.0, s - 2);
+  if (pi && pj) return 1.0 / ((double)(a - 1) * binom(s - 1, a - 1));
+  if (!pi && !pj) return 1.0 / ((double)(b - 1) * binom(s - 1, b - 1));
+  if (pj) return -1.0 / ((double)a * binom(s - 1, a)); /* i negated, j positive */
+  return -1.0 / ((double)b * binom(s - 1, b));         /* i positive, j negated */
+}
+
+/* iv[i * F + j] += w * coefficient, for every ordered pair of the cube's literals */
+static void credit_cube_iv(int kind, double w, const int32_t *sp, int na, const int32_t *sm, int nb, int F,
+                           double *iv) {
+  int32_t lit[2 * WO_MAXD];
+  int pos[2 * WO_MAXD];
+  int n = 0;
+  for (int k = 0; k < na; ++k) lit[n] = sp[k], pos[n++] = 1;
+  for (int k = 0; k < nb; ++k) lit[n] = sm[k], pos[n++] = 0;
+  for (int x = 0; x < n; ++x)
+    for (int y = 0; y < n; ++y)
+      if (x != y) iv[(int64_t)lit[x] * F + lit[y]] += w * cube_iv_coef(kind, na, nb, pos[x], pos[y]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -439,6 +473,89 @@ int wo_wdnf_bruteforce(int n_vars, int n_cubes, const double *w, const int32_t *
   return 0;
 }
 
+/* Interaction values of a WDNF by the per-cube formulas; out[i * n + j]. */
+int wo_wdnf_iv_values(int n_vars, int n_cubes, const double *w, const int32_t *lits, int max_lits, int kind,
+                      double *out) {
+  for (int64_t v = 0; v < (int64_t)n_vars * n_vars; ++v) out[v] = 0.0;
+  int32_t sp[WO_MAXD], sm[WO_MAXD];
+  for (int k = 0; k < n_cubes; ++k) {
+    int na = 0, nb = 0;
+    const int32_t *c = lits + (int64_t)k * max_lits;
+    for (int j = 0; j < max_lits; ++j) {
+      int32_t L = c[j];
+      if (L == 0) continue;
+      int32_t v = (L > 0 ? L : -L) - 1;
+      if (L > 0) { if (!set_has(sp, na, v)) sp[na++] = v; }
+      else { if (!set_has(sm, nb, v)) sm[nb++] = v; }
+    }
+    int bad = 0;
+    for (int i = 0; i < na; ++i)
+      if (set_has(sm, nb, sp[i])) bad = 1;
+    if (bad) continue;
+    credit_cube_iv(kind, w[k], sp, na, sm, nb, n_vars, out);
+  }
+  return 0;
+}
+
+/* The interaction definitions over a table of game values g[S] (S a bitmask
+ * of n players):
+ *   Shapley (Def. shap_iv_def): phi_{j|i=1} - phi_{j|i=0}, each a Shapley value
+ *     of j in the game on the other n - 1 players with i fixed;
+ *   Banzhaf (Def. banzhaf_iv_def): E[g | i,j in S] + E[g | i,j not in S]
+ *     - E[g | i in S, j not] - E[g | j in S, i not], S uniform.
+ * out[i * n + j], diagonal 0. */
+static void iv_from_game(int n, const double *g, int kind, double *out) {
+  int64_t N = (int64_t)1 << n;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      if (i != j) {
+        int64_t bi = (int64_t)1 << i, bj = (int64_t)1 << j;
+        /* sum over T subset of the players other than i and j */
+        double e11 = 0, e00 = 0, e10 = 0, e01 = 0;
+        for (int64_t T = 0; T < N; ++T) {
+          if (T & (bi | bj)) continue;
+          if (kind == WO_BANZHAF) {
+            e11 += g[T | bi | bj];
+            e00 += g[T];
+            e10 += g[T | bi];
+            e01 += g[T | bj];
+          } else {
+            /* Shapley value of j in an (n-1)-player game: weight of coalition T
+             * (|T| players besides j) is 1 / ((n-1) C(n-2, |T|)) */
+            int t = __builtin_popcountll((unsigned long long)T);
+            double wt = 1.0 / ((double)(n - 1) * binom(n - 2, t));
+            double with_i = g[T | bi | bj] - g[T | bi];   /* i always participates */
+            double without_i = g[T | bj] - g[T];          /* i always missing */
+            s += wt * (with_i - without_i);
+          }
+        }
+        if (kind == WO_BANZHAF) {
+          double cnt = ldexp(1.0, n - 2); /* subsets T per conditional expectation */
+          s = (e11 + e00 - e10 - e01) / cnt;
+        }
+      }
+      out[(int64_t)i * n + j] = s;
+    }
+  }
+}
+
+/* Interaction values of a WDNF from the definitions over all 2^n assignments. */
+int wo_wdnf_iv_bruteforce(int n_vars, int n_cubes, const double *w, const int32_t *lits, int max_lits, int kind,
+                          double *out) {
+  if (n_vars > 20 || n_vars < 2) return -1;
+  uint8_t x[32];
+  int64_t N = (int64_t)1 << n_vars;
+  double *F = (double *)malloc(sizeof(double) * (size_t)N);
+  for (int64_t a = 0; a < N; ++a) {
+    for (int v = 0; v < n_vars; ++v) x[v] = (uint8_t)((a >> v) & 1);
+    F[a] = wo_wdnf_eval(n_cubes, w, lits, max_lits, x);
+  }
+  iv_from_game(n_vars, F, kind, out);
+  free(F);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Background SHAP: Formula trival_bg with the four rules                    */
 /* ------------------------------------------------------------------------ */
@@ -515,6 +632,7 @@ typedef struct {
   double scale;
   double *phi;
   int64_t base;
+  double *iv; /* when set: interaction values [F][F] instead of phi */
 } walk_state;
 
 /* At an inner node with feature f (c and b take directions gc, gb):
@@ -526,7 +644,10 @@ static void walk(walk_state *S, int64_t nd, int32_t *sp, int na, int32_t *sm, in
   const wo_model *M = S->M;
   int32_t f = M->feature[nd];
   if (f < 0) {
-    credit_cube(S->kind, S->scale * (double)M->value[nd], sp, na, sm, nb, S->phi);
+    if (S->iv)
+      credit_cube_iv(S->kind, S->scale * (double)M->value[nd], sp, na, sm, nb, M->n_features, S->iv);
+    else
+      credit_cube(S->kind, S->scale * (double)M->value[nd], sp, na, sm, nb, S->phi);
     return;
   }
   int64_t lc = S->base + M->left[nd], rc = S->base + M->right[nd];
@@ -566,7 +687,7 @@ static void walk_row(void *vctx, int64_t r) {
   double *acc = (double *)calloc((size_t)F, sizeof(double));
   load_row(X->C, X->ldc, r, F, c);
   int32_t sp[WO_MAXD], sm[WO_MAXD];
-  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, acc, 0};
+  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, acc, 0, NULL};
   for (int64_t k = 0; k < X->m; ++k) {
     load_row(X->B, X->ldb, k, F, b);
     for (int t = 0; t < M->n_trees; ++t) {
@@ -584,6 +705,38 @@ int wo_bg_walk(const wo_model *M, const float *C, int64_t n, int64_t ldc, const 
                int64_t ldb, int kind, double *phi, int64_t ldphi, int threads) {
   walkrows_ctx ctx = {M, C, ldc, B, m, ldb, kind, phi, ldphi};
   parallel_rows(n, threads, walk_row, &ctx);
+  return 0;
+}
+
+static void iv_walk_row(void *vctx, int64_t r) {
+  walkrows_ctx *X = (walkrows_ctx *)vctx;
+  const wo_model *M = X->M;
+  int F = M->n_features;
+  double *c = (double *)malloc(sizeof(double) * (size_t)F);
+  double *b = (double *)malloc(sizeof(double) * (size_t)F);
+  double *acc = (double *)calloc((size_t)F * (size_t)F, sizeof(double));
+  load_row(X->C, X->ldc, r, F, c);
+  int32_t sp[WO_MAXD], sm[WO_MAXD];
+  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, NULL, 0, acc};
+  for (int64_t k = 0; k < X->m; ++k) {
+    load_row(X->B, X->ldb, k, F, b);
+    for (int t = 0; t < M->n_trees; ++t) {
+      S.base = M->node_offset[t];
+      walk(&S, S.base, sp, 0, sm, 0);
+    }
+  }
+  for (int64_t q = 0; q < (int64_t)F * F; ++q) X->phi[q * X->ldphi + r] = acc[q];
+  free(acc);
+  free(b);
+  free(c);
+}
+
+/* Background interaction values: iv[(i * F + j) * ldphi + r] for consumer r,
+ * the pair (i, j) of features, diagonal 0. */
+int wo_bg_iv_walk(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B, int64_t m,
+                  int64_t ldb, int kind, double *iv, int64_t ldphi, int threads) {
+  walkrows_ctx ctx = {M, C, ldc, B, m, ldb, kind, iv, ldphi};
+  parallel_rows(n, threads, iv_walk_row, &ctx);
   return 0;
 }
 
@@ -637,6 +790,46 @@ static void brute_row(void *vctx, int64_t r) {
   free(h);
   free(b);
   free(c);
+}
+
+static void iv_brute_row(void *vctx, int64_t r) {
+  brute_ctx *X = (brute_ctx *)vctx;
+  const wo_model *M = X->M;
+  int F = M->n_features;
+  int64_t N = (int64_t)1 << F;
+  double *c = (double *)malloc(sizeof(double) * (size_t)F);
+  double *b = (double *)malloc(sizeof(double) * (size_t)F);
+  double *h = (double *)malloc(sizeof(double) * (size_t)F);
+  double *v = (double *)calloc((size_t)N, sizeof(double));
+  double *out = (double *)malloc(sizeof(double) * (size_t)F * (size_t)F);
+  load_row(X->C, X->ldc, r, F, c);
+  for (int64_t k = 0; k < X->m; ++k) {
+    load_row(X->B, X->ldb, k, F, b);
+    for (int64_t S = 0; S < N; ++S) {
+      for (int f = 0; f < F; ++f) h[f] = ((S >> f) & 1) ? c[f] : b[f];
+      double s = 0.0;
+      for (int t = 0; t < M->n_trees; ++t) s += tree_predict(M, t, h);
+      v[S] += s;
+    }
+  }
+  for (int64_t S = 0; S < N; ++S) v[S] /= (double)X->m;
+  iv_from_game(F, v, X->kind, out);
+  for (int64_t q = 0; q < (int64_t)F * F; ++q) X->phi[q * X->ldphi + r] = out[q];
+  free(out);
+  free(v);
+  free(h);
+  free(b);
+  free(c);
+}
+
+/* Interaction values from their definitions on the Background-SHAP game
+ * (F <= 20); layout as wo_bg_iv_walk. */
+int wo_bg_iv_bruteforce(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B, int64_t m,
+                        int64_t ldb, int kind, double *iv, int64_t ldphi, int threads) {
+  if (M->n_features > 20 || M->n_features < 2) return -1;
+  brute_ctx ctx = {M, C, ldc, B, m, ldb, kind, iv, ldphi};
+  parallel_rows(n, threads, iv_brute_row, &ctx);
+  return 0;
 }
 
 int wo_bg_bruteforce(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B,

@@ -383,3 +383,72 @@ def test_binomial_form_of_coefficients():
             lhs = math.factorial(a - 1) * math.factorial(b) / math.factorial(a + b)
             rhs = 1.0 / (a * math.comb(a + b, a))
             assert abs(lhs - rhs) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Interaction values (Section 3: Def. shap_iv_def, Table table_shap_iv,
+# Def. banzhaf_iv_def, Formula banzhaf_simplified_formula_interactions)
+# ---------------------------------------------------------------------------
+
+def test_iv_single_cube_closed_forms():
+    # w (x1 and x2): fixing x1 = 1 leaves w x2 (Shapley value of x2: w); fixing
+    # x1 = 0 leaves 0, so both interaction values are w
+    for kind in (oracle.SHAPLEY, oracle.BANZHAF):
+        iv = oracle.wdnf_iv_values([(3.0, [1, 2])], 2, kind)
+        np.testing.assert_allclose(iv, [[0.0, 3.0], [3.0, 0.0]], atol=1e-15)
+        np.testing.assert_allclose(oracle.wdnf_iv_bruteforce([(3.0, [1, 2])], 2, kind), iv, atol=1e-15)
+    # w (x1 and not x2): x1 = 1 leaves w (not x2), whose Shapley value for x2 is -w
+    iv = oracle.wdnf_iv_values([(2.0, [1, -2])], 2, oracle.SHAPLEY)
+    np.testing.assert_allclose(iv, [[0.0, -2.0], [-2.0, 0.0]], atol=1e-15)
+    # a variable outside the cube interacts with nothing; a contradictory cube is dropped
+    iv = oracle.wdnf_iv_values([(1.0, [1, 2]), (5.0, [3, -3])], 4, oracle.SHAPLEY)
+    assert np.all(iv[2:, :] == 0) and np.all(iv[:, 2:] == 0)
+
+
+def test_iv_three_literal_cube_by_hand():
+    # w (x1 and x2 and not x3), S+ = {1, 2}, S- = {3}, |S| = 3 (Table table_shap_iv):
+    #   both positive: w / ((2 - 1) C(2, 1)) = w / 2
+    #   x1 positive, x3 negated: -w / (1 * C(2, 1)) = -w / 2 (either order)
+    w = 6.0
+    iv = oracle.wdnf_iv_values([(w, [1, 2, -3])], 3, oracle.SHAPLEY)
+    expect = np.array([[0, w / 2, -w / 2], [w / 2, 0, -w / 2], [-w / 2, -w / 2, 0]])
+    np.testing.assert_allclose(iv, expect, atol=1e-14)
+    np.testing.assert_allclose(oracle.wdnf_iv_bruteforce([(w, [1, 2, -3])], 3, oracle.SHAPLEY), expect, atol=1e-14)
+    # Banzhaf: +-w / 2^(|S| - 2) = +-w / 2
+    ivb = oracle.wdnf_iv_values([(w, [1, 2, -3])], 3, oracle.BANZHAF)
+    np.testing.assert_allclose(ivb, expect, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("kind", [oracle.SHAPLEY, oracle.BANZHAF])
+def test_iv_formulas_equal_definitions_random_wdnf(seed, kind):
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(3, 8))
+    cubes = []
+    for _ in range(int(rng.integers(1, 7))):
+        k = int(rng.integers(1, n + 1))
+        vs = rng.choice(n, k, replace=False) + 1
+        cubes.append((float(rng.normal()), [int(v) * (1 if rng.random() < 0.6 else -1) for v in vs]))
+    iv = oracle.wdnf_iv_values(cubes, n, kind)
+    np.testing.assert_allclose(iv, oracle.wdnf_iv_bruteforce(cubes, n, kind), atol=1e-12)
+    np.testing.assert_allclose(iv, iv.T, atol=1e-12)
+    assert np.all(np.diag(iv) == 0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("kind", [oracle.SHAPLEY, oracle.BANZHAF])
+def test_bg_iv_walk_equals_definitions_random_trees(seed, kind):
+    M, C, B = _random_case(300 + seed, pool=3 if seed % 2 else 0)
+    ref = oracle.bg_iv_bruteforce(M, C, B, kind)
+    got = oracle.bg_iv_walk(M, C, B, kind)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+    np.testing.assert_allclose(got, got.transpose(1, 0, 2), atol=1e-12)
+
+
+def test_bg_iv_of_unused_features_is_zero():
+    M, C, B = _random_case(377, n_features=6, pool=3)
+    iv = oracle.bg_iv_walk(M, C, B)
+    used = np.unique(M.ens.feature[M.ens.feature >= 0])
+    unused = np.setdiff1d(np.arange(6), used)
+    assert unused.size > 0
+    assert np.all(iv[unused] == 0) and np.all(iv[:, unused] == 0)
