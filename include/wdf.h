@@ -57,7 +57,9 @@ enum {
 /* Values computed from the cube of a (consumer, background) pattern pair. */
 enum {
   WDF_SHAPLEY = 0,          /* Formula shap_simplified_formula */
-  WDF_BANZHAF = 1           /* Formula banzhaf_simplified_formula */
+  WDF_BANZHAF = 1,          /* Formula banzhaf_simplified_formula */
+  WDF_SHAPLEY_IV = 2,       /* interaction values: Def. shap_iv_def, Table table_shap_iv */
+  WDF_BANZHAF_IV = 3        /* Def. banzhaf_iv_def, Formula banzhaf_simplified_formula_interactions */
 };
 
 /* Kernel choice for the pattern, histogram and gather steps. */
@@ -127,7 +129,10 @@ int wdf_model_specialised(const wdf_model *model);
  * exact uint32 histograms, then (MFMA) the tables
  *     t_q[k][p] = (w_l/m) (M h_l)[p] + (w_r/m) (M h_r)[p ^ 1]
  * for the values selected by `values` (WDF_SHAPLEY / WDF_BANZHAF), and the base
- * value mean_b f(b).  B is column-major (B[f * ldb + r]), m >= 1 rows, on the
+ * value mean_b f(b).  With WDF_SHAPLEY_IV / WDF_BANZHAF_IV the tables are per
+ * pair of path positions instead (C(d,2) tables of 2^d entries per group,
+ * from coefficient matrices of the same four-rule cubes valued by the
+ * interaction formulas of Section 3), for wdf_explain_iv.  B is column-major (B[f * ldb + r]), m >= 1 rows, on the
  * device when b_on_device is nonzero, else on the host (copied in).  Work is
  * enqueued on `hip_stream` (NULL = the HIP null stream) and the call
  * returns after it finishes, so B may be freed on return.  The summary owns
@@ -138,7 +143,8 @@ int wdf_background_load(wdf_model *model, const float *B, int64_t m, int64_t ldb
 
 /* Path-Dependent variant (Section 8, Formula eq:path_dependent_estimation):
  * the background histogram is replaced by the cover-product frequency of every
- * pattern; the model must have been loaded with covers.  Same output handle. */
+ * pattern; the model must have been loaded with covers.  Same output handle.
+ * WDF_SHAPLEY or WDF_BANZHAF only. */
 int wdf_pathdep_load(wdf_model *model, int values, void *hip_stream, wdf_bg **out);
 
 void wdf_bg_destroy(wdf_bg *bg);
@@ -152,6 +158,19 @@ void wdf_bg_destroy(wdf_bg *bg);
  * Errors: INVALID_ARG, DEVICE. */
 int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi,
                 void *hip_stream);
+
+/* Interaction values phi_{i,j} (i != j) of consumer rows, for a summary
+ * loaded with WDF_SHAPLEY_IV or WDF_BANZHAF_IV (Section 3; by linearity the
+ * Background game's interaction values are the per-cube formulas summed over
+ * leaves and background rows, as for Shapley values, Section 7).  X: device
+ * [F][ldx >= n]; iv: device [F * F][ldiv >= n], iv[(i * F + j) * ldiv + r]
+ * for consumer r, symmetric in (i, j), diagonal 0.  Runs the generic
+ * interaction kernel (per-lane LDS accumulators); needs F <= 640.
+ * Asynchronous on hip_stream; allocates nothing.
+ * Errors: INVALID_ARG (NULL, sizes, summary not of an interaction kind),
+ * UNSUPPORTED (F > 640), DEVICE. */
+int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
+                   void *hip_stream);
 
 /* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
  * f(c) - base).  For a path-dependent summary: the cover-weighted mean.  After

@@ -168,6 +168,47 @@ static void build_coef_matrix(int d, int values, std::vector<double> &M) {
   }
 }
 
+// Interaction coefficients (Section 3): M[(q * 2^d + pc) * 2^d + pb] for the
+// pair q = (u, v), u < v, of distinct-feature positions: with the cube of
+// (pc, pb) built by the same four rules, a = |S+|, b = |S-|, s = a + b, and u, v
+// both in the cube: Shapley (Table table_shap_iv) 1/((a-1) C(s-1, a-1)) when
+// both are positive, 1/((b-1) C(s-1, b-1)) when both are negated, and
+// -1/(a C(s-1, a)) (= -1/(b C(s-1, b))) when the signs differ; Banzhaf
+// (Formula banzhaf_simplified_formula_interactions) +-1/2^(s-2), + for equal
+// signs.  0 when u or v is not in the cube or the cube is false.
+static void build_iv_matrix(int d, int kind, std::vector<double> &M) {
+  const int P = 1 << d, Q = d * (d - 1) / 2;
+  M.assign((size_t)Q * P * P, 0.0);
+  for (int pc = 0; pc < P; ++pc) {
+    for (int pb = 0; pb < P; ++pb) {
+      if (((~pc) & (~pb)) & (P - 1)) continue;
+      const int posm = pc & ~pb & (P - 1), negm = ~pc & pb & (P - 1);
+      const int a = __builtin_popcount(posm), b = __builtin_popcount(negm), s = a + b;
+      if (s < 2) continue;
+      int q = 0;
+      for (int u = 0; u < d; ++u) {
+        for (int v = u + 1; v < d; ++v, ++q) {
+          const int bu = 1 << (d - 1 - u), bv = 1 << (d - 1 - v);
+          const bool iu = (posm | negm) & bu, iv = (posm | negm) & bv;
+          if (!iu || !iv) continue;
+          const bool pu = posm & bu, pv = posm & bv;
+          double c;
+          if (kind == 1) {
+            c = std::ldexp(pu == pv ? 1.0 : -1.0, -(s - 2));
+          } else if (pu && pv) {
+            c = 1.0 / (double(a - 1) * binomial(s - 1, a - 1));
+          } else if (!pu && !pv) {
+            c = 1.0 / (double(b - 1) * binomial(s - 1, b - 1));
+          } else {
+            c = -1.0 / (double(a) * binomial(s - 1, a));
+          }
+          M[((size_t)q * P + pc) * P + pb] = c;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Model
 // ---------------------------------------------------------------------------
@@ -445,13 +486,72 @@ extern "C" int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32
 // (torch's default stream is the null stream).
 static hipStream_t pick_stream(wdf_ctx *, void *s) { return (hipStream_t)s; }
 
+// Interaction layout and coefficient matrices, prepared once per model and
+// kind (the caller holds the model's workspace lock).
+static int prepare_iv(wdf_model *M, int kind) {
+  hipStream_t s = M->ctx->stream;
+  int rc;
+  if (!M->iv_layout) {
+    const size_t G = M->groups.size();
+    M->iv_off.assign(G, 0);
+    int64_t off = 0;
+    for (size_t g = 0; g < G; ++g) {
+      const int d = M->groups[g].depth;
+      M->iv_off[g] = off;
+      off += ((((int64_t)d * (d - 1) / 2) << d) + 3) & ~(int64_t)3;
+    }
+    M->iv_tab_size = off;
+    int64_t so = 0;
+    for (int dp = 0; dp <= WDF_MAX_DEPTH; ++dp) {
+      M->s_iv_class_off[dp] = so;
+      so += (int64_t)M->cls[dp].ncols * (dp * (dp - 1) / 2) << dp;
+    }
+    M->s_iv_total = so;
+    // per feature: (group, position) of every first occurrence on a path
+    const int F = M->n_features;
+    std::vector<std::vector<int32_t>> lists((size_t)F);
+    for (size_t g = 0; g < G; ++g) {
+      const Group &gr = M->groups[g];
+      for (int k = 0; k < gr.depth; ++k) {
+        const PathNode &pn = M->path[(size_t)gr.path_off + k];
+        if (!pn.first) continue;
+        lists[(size_t)pn.feat].push_back((int32_t)g);
+        lists[(size_t)pn.feat].push_back(k);
+      }
+    }
+    std::vector<int32_t> foff((size_t)F + 1, 0), ent;
+    for (int f = 0; f < F; ++f) {
+      foff[(size_t)f + 1] = foff[(size_t)f] + (int32_t)(lists[(size_t)f].size() / 2);
+      ent.insert(ent.end(), lists[(size_t)f].begin(), lists[(size_t)f].end());
+    }
+    if (ent.empty()) ent.assign(2, 0);
+    std::vector<int64_t> soff(M->s_iv_class_off, M->s_iv_class_off + WDF_MAX_DEPTH + 1);
+    if ((rc = upload(M->d_iv_off, M->iv_off.empty() ? std::vector<int64_t>(1, 0) : M->iv_off, s))) return rc;
+    if ((rc = upload(M->d_siv_class_off, soff, s))) return rc;
+    if ((rc = upload(M->d_ivf_off, foff, s))) return rc;
+    if ((rc = upload(M->d_iv_entries, ent, s))) return rc;
+    M->iv_layout = true;
+  }
+  if (!M->iv_coef_ready[kind]) {
+    for (int dp = 2; dp <= WDF_MAX_DEPTH; ++dp) {
+      if (M->cls[dp].ncols == 0) continue;
+      std::vector<double> coef;
+      build_iv_matrix(dp, kind, coef);
+      if ((rc = upload(M->d_coef_iv[kind][dp], coef, s))) return rc;
+    }
+    M->iv_coef_ready[kind] = true;
+  }
+  return WDF_OK;
+}
+
 // Table storage of a summary, zeroed once (the padding between tables is never
 // written again).
 static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
   int rc;
-  if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(M->tab_size, 1) * sizeof(float)))) return rc;
+  const int64_t n = bg->iv ? M->iv_tab_size : M->tab_size;
+  if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float)))) return rc;
   HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));
-  if (M->jit) {
+  if (M->jit && !bg->iv) {
     if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->jp.xtab_size, 1) * sizeof(float)))) return rc;
     HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
   }
@@ -465,6 +565,20 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
   const int64_t G = (int64_t)M->groups.size();
   HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
                          M->d_hclass_off.as<int64_t>(), H, s));
+  if (bg->iv) {  // pair products per class, then pair tables
+    const int kind = bg->values - WDF_SHAPLEY_IV;
+    for (int dp = 2; dp <= WDF_MAX_DEPTH; ++dp) {
+      const ClassInfo &c = M->cls[dp];
+      if (c.ncols == 0) continue;
+      const int K = 1 << dp, R = dp * (dp - 1) / 2 * K;
+      HIP_TRY(launch_gemm_f64(M->d_coef_iv[kind][dp].as<double>(), H + c.h_off, S + M->s_iv_class_off[dp], R, K,
+                              c.ncols, s));
+    }
+    HIP_TRY(launch_expand_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_off.as<int64_t>(),
+                             M->d_siv_class_off.as<int64_t>(), S, bg->d_tab.as<float>(), s));
+    HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
+    return WDF_OK;
+  }
   for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
     const ClassInfo &c = M->cls[dp];
     if (c.ncols == 0) continue;
@@ -487,7 +601,8 @@ static int contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double
   DevBuf &H = M->ws_H, &S = M->ws_S, &base = M->ws_base;
   int rc;
   if ((rc = ws_reserve(H, (size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
-  if ((rc = ws_reserve(S, (size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
+  if ((rc = ws_reserve(S, (size_t)std::max<int64_t>(bg->iv ? M->s_iv_total : M->s_total, 1) * sizeof(double))))
+    return rc;
   if ((rc = ws_reserve(base, sizeof(double)))) return rc;
   if ((rc = alloc_tables(M, bg, s))) return rc;
   if ((rc = enqueue_contract(M, bg, hist, freq, scale, H.as<double>(), S.as<double>(), base.as<double>(), s)))
@@ -503,7 +618,7 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   *out = nullptr;
   if (m < 1 || ldb < m) return set_error(WDF_E_INVALID_ARG, "wdf_background_load: need m >= 1 and ldb >= m");
   if (m > 0xFFFFFFFFll) return set_error(WDF_E_UNSUPPORTED, "wdf_background_load: m exceeds uint32 counts");
-  if (values != WDF_SHAPLEY && values != WDF_BANZHAF)
+  if (values < WDF_SHAPLEY || values > WDF_BANZHAF_IV)
     return set_error(WDF_E_INVALID_ARG, "wdf_background_load: unknown value kind %d", values);
   HIP_TRY(hipSetDevice(M->ctx->device));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
@@ -514,6 +629,11 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   bg->device = M->device;
   bg->m = m;
   bg->values = values;
+  bg->iv = values >= WDF_SHAPLEY_IV;
+  if (bg->iv) {
+    int rc_iv;
+    if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
+  }
   int rc;
   DevBuf Bcopy;
   const float *Bd = B;
@@ -547,7 +667,9 @@ static int ensure_refresh_workspace(wdf_bg *bg) {
       (rc = bg->own_codes.alloc((size_t)M->jp.words * (size_t)bg->m * sizeof(uint32_t))))
     return rc;
   if (!bg->own_H.ptr && (rc = bg->own_H.alloc((size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
-  if (!bg->own_S.ptr && (rc = bg->own_S.alloc((size_t)std::max<int64_t>(M->s_total, 1) * sizeof(double)))) return rc;
+  if (!bg->own_S.ptr &&
+      (rc = bg->own_S.alloc((size_t)std::max<int64_t>(bg->iv ? M->s_iv_total : M->s_total, 1) * sizeof(double))))
+    return rc;
   if (!bg->d_base.ptr && (rc = bg->d_base.alloc(sizeof(double)))) return rc;
   return WDF_OK;
 }
@@ -648,7 +770,8 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   *out = nullptr;
   if (!M->has_cover) return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: the model was loaded without covers");
   if (values != WDF_SHAPLEY && values != WDF_BANZHAF)
-    return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: unknown value kind %d", values);
+    return set_error(WDF_E_INVALID_ARG, "wdf_pathdep_load: value kind %d (interaction kinds need a background)",
+                     values);
   HIP_TRY(hipSetDevice(M->ctx->device));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
   std::unique_ptr<wdf_bg> bg(new (std::nothrow) wdf_bg());
@@ -658,6 +781,11 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   bg->device = M->device;
   bg->m = 0;
   bg->values = values;
+  bg->iv = values >= WDF_SHAPLEY_IV;
+  if (bg->iv) {
+    int rc_iv;
+    if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
+  }
   bg->pathdep = true;
   int rc;
   if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(double)))) return rc;
@@ -697,11 +825,29 @@ extern "C" int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t 
   if (n < 0 || ldx < n || ldphi < n) return set_error(WDF_E_INVALID_ARG, "wdf_explain: need 0 <= n <= ldx, ldphi");
   if (n == 0) return WDF_OK;
   if (!X || !phi) return set_error(WDF_E_INVALID_ARG, "wdf_explain: NULL X or phi");
+  if (bg->iv) return set_error(WDF_E_INVALID_ARG, "wdf_explain: an interaction summary: use wdf_explain_iv");
   wdf_model *M = bg->model;
   hipStream_t s = pick_stream(M->ctx, hip_stream);
   if (M->jit) return jit_explain(bg, X, n, ldx, phi, ldphi, s);
   HIP_TRY(launch_explain_generic(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(),
                                  bg->d_tab.as<float>(), X, n, ldx, phi, ldphi, M->n_features, s));
+  return WDF_OK;
+}
+
+extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
+                              void *hip_stream) {
+  if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: NULL summary");
+  if (!bg->iv) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: not an interaction summary");
+  if (n < 0 || ldx < n || ldiv < n) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: need 0 <= n <= ldx, ldiv");
+  if (n == 0) return WDF_OK;
+  if (!X || !iv) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: NULL X or iv");
+  wdf_model *M = bg->model;
+  if (M->n_features > kMaxFeaturesIV)
+    return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %d features exceeds %d", M->n_features, kMaxFeaturesIV);
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), M->d_iv_off.as<int64_t>(),
+                            M->d_ivf_off.as<int32_t>(), M->d_iv_entries.as<int2>(), bg->d_tab.as<float>(), X, n, ldx,
+                            iv, ldiv, M->n_features, s));
   return WDF_OK;
 }
 
@@ -736,7 +882,7 @@ extern "C" int64_t wdf_debug_histograms(const wdf_bg *bg, uint32_t *host_out, in
 
 extern "C" int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap) {
   if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_debug_tables: NULL summary");
-  const int64_t n = bg->model->tab_size;
+  const int64_t n = bg->iv ? bg->model->iv_tab_size : bg->model->tab_size;
   if (host_out) {
     if (cap < n) return set_error(WDF_E_INVALID_ARG, "wdf_debug_tables: capacity %lld < %lld", (long long)cap,
                                   (long long)n);

@@ -122,6 +122,17 @@ struct wdf_model {
   wdf::DevBuf ws_codes, ws_H, ws_S, ws_base;
 
   std::atomic<int> n_bg{0};  // live background summaries (their tables follow the current plan)
+
+  // interaction values (prepared at the first summary of an interaction kind):
+  // per group the offset of its pair tables, per class the offset of its
+  // products, per feature the (group, position) list of its first occurrences
+  bool iv_layout = false;
+  std::vector<int64_t> iv_off;
+  int64_t iv_tab_size = 0, s_iv_total = 0;
+  int64_t s_iv_class_off[WDF_MAX_DEPTH + 1] = {};
+  wdf::DevBuf d_iv_off, d_siv_class_off, d_ivf_off, d_iv_entries;
+  bool iv_coef_ready[2] = {false, false};
+  wdf::DevBuf d_coef_iv[2][WDF_MAX_DEPTH + 1];  // [Shapley/Banzhaf][dprime]
 };
 
 struct wdf_bg {
@@ -129,6 +140,7 @@ struct wdf_bg {
   int device = 0;
   int64_t m = 0;
   int values = WDF_SHAPLEY;
+  bool iv = false;      // an interaction kind: pair tables in d_tab, no explain tables
   bool pathdep = false;
   double base = 0.0;
   wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)

@@ -381,6 +381,113 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Interaction values (Section 3): tables per pair of path positions
+// ---------------------------------------------------------------------------
+
+// index of the unordered pair (a, b), a < b, among n positions
+__device__ __forceinline__ int pair_index(int a, int b, int n) { return a * (2 * n - a - 1) / 2 + (b - a - 1); }
+
+// tab_iv[iv_off[g] + q * 2^d + p] for the pair q = (k1, k2), k1 < k2, of path
+// positions: the contraction product of the pair of distinct features at
+// (merge(k1), merge(k2)) for the left leaf's merged pattern, plus the right
+// leaf's for p ^ 1; 0 unless both positions are their feature's first.
+__global__ __launch_bounds__(256) void k_expand_iv(const Group *__restrict__ groups,
+                                                   const PathNode *__restrict__ path,
+                                                   const int64_t *__restrict__ iv_off,
+                                                   const int64_t *__restrict__ s_class_off,
+                                                   const double *__restrict__ S, float *__restrict__ tab) {
+  const int gi = blockIdx.x;
+  const Group g = groups[gi];
+  if (g.depth < 2) return;
+  const int d = g.depth, dp = g.dprime;
+  const int64_t K = 1 << dp, R = (int64_t)(dp * (dp - 1) / 2) * K;
+  const PathNode *pn = path + g.path_off;
+  const double *Sc = S + s_class_off[dp];
+  const int total = (d * (d - 1) / 2) << d;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int q = idx >> d;
+    const uint32_t p = (uint32_t)(idx & ((1 << d) - 1));
+    int k1 = 0, rest = q;  // decode q = pair_index(k1, k2, d)
+    while (rest >= d - 1 - k1) rest -= d - 1 - k1, ++k1;
+    const int k2 = k1 + 1 + rest;
+    double v = 0.0;
+    if (pn[k1].first && pn[k2].first) {
+      const int u = min((int)pn[k1].merge, (int)pn[k2].merge), w = max((int)pn[k1].merge, (int)pn[k2].merge);
+      const int64_t row = (int64_t)pair_index(u, w, dp) * K;
+      v = Sc[(int64_t)g.col_l * R + row + merge_pattern(pn, d, dp, p)];
+      if (g.col_r >= 0) v += Sc[(int64_t)g.col_r * R + row + merge_pattern(pn, d, dp, p ^ 1u)];
+    }
+    tab[iv_off[gi] + idx] = (float)v;
+  }
+}
+
+// Interaction values of consumer rows: one wave = 64 rows and one feature i
+// (blockIdx.y).  The wave walks the groups whose path carries i (first
+// occurrence, list [feat_off[i], feat_off[i+1]) of (group, position)), finds
+// each row's pattern and adds the pair tables into per-lane accumulators of
+// every other feature j of the path, kept in LDS ([wave][j][lane]: the lanes
+// of a wave add to one j at a time, 64 consecutive words).  Then row r's
+// iv[(i * F + j) * ldo + r] = acc[j] for all j (diagonal 0).
+__global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ groups,
+                                                    const PathNode *__restrict__ path,
+                                                    const int64_t *__restrict__ iv_off,
+                                                    const int32_t *__restrict__ feat_off,
+                                                    const int2 *__restrict__ entries,
+                                                    const float *__restrict__ tab, const float *__restrict__ X,
+                                                    int64_t n, int64_t ldx, float *__restrict__ out, int64_t ldo,
+                                                    int F) {
+  extern __shared__ float acc_all[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int i = blockIdx.y;
+  const int64_t row = ((int64_t)blockIdx.x * waves + wave) * 64 + lane;
+  const int64_t rr = row < n ? row : n - 1;
+  float *acc = acc_all + (int64_t)wave * F * 64;
+  for (int j = 0; j < F; ++j) acc[j * 64 + lane] = 0.f;
+  for (int e = feat_off[i]; e < feat_off[i + 1]; ++e) {
+    const int2 en = entries[e];
+    const Group g = groups[en.x];
+    const PathNode *pn = path + g.path_off;
+    const int d = g.depth, k1 = en.y;
+    uint32_t p = 0;
+    for (int k = 0; k < d; ++k) {
+      const float x = X[(int64_t)pn[k].feat * ldx + rr];
+      const bool left = x != x ? pn[k].dl != 0 : x < pn[k].thr;
+      p = 2u * p + (left == (pn[k].dir == 0) ? 1u : 0u);
+    }
+    const float *T = tab + iv_off[en.x];
+    for (int k2 = 0; k2 < d; ++k2) {
+      if (k2 == k1 || !pn[k2].first) continue;
+      const int q = k1 < k2 ? pair_index(k1, k2, d) : pair_index(k2, k1, d);
+      acc[pn[k2].feat * 64 + lane] += T[((int64_t)q << d) + p];
+    }
+  }
+  if (row < n)
+    for (int j = 0; j < F; ++j) out[((int64_t)i * F + j) * ldo + row] = acc[j * 64 + lane];
+}
+
+hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
+                            const int64_t *s_class_off, const double *S, float *tab, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_iv, dim3((unsigned)n_groups), dim3(256), 0, s, groups, path, iv_off, s_class_off, S,
+                     tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, const int64_t *iv_off,
+                             const int32_t *feat_off, const int2 *entries, const float *tab, const float *X,
+                             int64_t n, int64_t ldx, float *out, int64_t ldo, int F, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int waves = (int)((160 * 1024) / ((int64_t)F * 64 * 4));
+  waves = waves > 4 ? 4 : waves;
+  if (waves < 1) return hipErrorInvalidValue;  // the caller checks F first
+  const size_t lds = (size_t)waves * F * 64 * sizeof(float);
+  const int64_t blocks = (n + 64 * waves - 1) / (64 * waves);
+  hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F), dim3(64 * waves), lds, s, groups, path, iv_off,
+                     feat_off, entries, tab, X, n, ldx, out, ldo, F);
+  return hipGetLastError();
+}
+
 // Explain tables from the gather tables: each unit re-indexed by raw splits
 // and laid out in float4 planes; quads built from their two pair tables.  For a quad of pair depth d, entry I (d+1 bits:
 // prefix, s_a, s_aL, s_aR) has the left pair pattern (prefix, s_a, s_aL) and

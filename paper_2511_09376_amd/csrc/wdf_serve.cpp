@@ -202,6 +202,7 @@ extern "C" int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_ro
                                  wdf_server **out) {
   if (!bg || !out) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: NULL argument");
   *out = nullptr;
+  if (bg->iv) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: serving explains Shapley/Banzhaf values");
   if (max_rows < 1 || queue_cap < 1)
     return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: max_rows and queue_cap must be >= 1");
   const int F = bg->model->n_features;

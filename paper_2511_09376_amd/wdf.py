@@ -31,6 +31,8 @@ E_COMPILE = -7
 
 SHAPLEY = 0
 BANZHAF = 1
+SHAPLEY_IV = 2             # interaction values (Def. shap_iv_def)
+BANZHAF_IV = 3             # Def. banzhaf_iv_def
 
 KERNEL_AUTO = 0
 KERNEL_GENERIC = 1
@@ -98,7 +100,7 @@ class Tuning(C.Structure):
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
-    "wdf_base_value", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
+    "wdf_base_value", "wdf_explain_iv", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
     "wdf_debug_specialised_source", "wdf_model_autotune", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
@@ -126,6 +128,7 @@ def lib():
         L.wdf_bg_destroy.argtypes = [P]
         L.wdf_explain.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_base_value.argtypes = [P, C.POINTER(C.c_double)]
+        L.wdf_explain_iv.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_background_refresh.argtypes = [P, P, I64, P]
         L.wdf_graph_create.argtypes = [P, P, I64, P, I64, I64, P, I64, C.POINTER(P)]
         L.wdf_graph_launch.argtypes = [P, P]
@@ -326,6 +329,25 @@ class Background:
         ldp = out.stride(0) if n else 0
         _check(lib().wdf_explain(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldp,
                                  _stream_handle(stream)))
+        return out
+
+    def explain_iv(self, X, out=None, stream=None):
+        """Interaction values [n_features, n_features, n] (float32 CUDA tensor,
+        symmetric, diagonal 0) of consumer rows X [n_features, n]; the summary
+        must have been loaded with SHAPLEY_IV or BANZHAF_IV."""
+        import torch
+        F = self.model.n_features
+        X = _colmajor_tensor(X, F, "X")
+        n = X.shape[1]
+        if out is None:
+            out = torch.empty((F, F, n), dtype=torch.float32, device=X.device)
+        if out.shape != (F, F, n) or out.dtype != torch.float32 or (n > 1 and out.stride(2) != 1) or \
+                out.stride(1) != out.stride(0) // F:
+            raise ValueError("out must be float32 [F, F, n] with rows contiguous")
+        ldx = X.stride(0) if n else 0
+        ldo = out.stride(1) if n else 0
+        _check(lib().wdf_explain_iv(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldo,
+                                    _stream_handle(stream)))
         return out
 
     def refresh(self, B, stream=None):
