@@ -27,6 +27,7 @@ from paper_2511_09376_amd import synth  # noqa: E402
 
 METRIC = "Background-SHAP rows/s (100 trees d6, 127 feat) + served p50/p99 latency"
 VALU_PEAK_OPS = 256 * 64 * 2.4e9   # 32-bit lane operations per second (non-packed)
+HBM_PEAK = 8.0e12                  # bytes per second
 
 DESCRIPTIONS = {
     "paper": "paper-scale shape: 100 complete depth-6 trees, 127 features (normal/log-normal/binary/count mix, 5% NaN), 3M consumer rows x 5M background rows",
@@ -174,8 +175,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
-    ap.add_argument("--values", default="shapley", choices=["shapley", "banzhaf"],
-                    help="value kind: Shapley (default) or Banzhaf values of the same game")
+    ap.add_argument("--values", default="shapley", choices=["shapley", "banzhaf", "shapley_iv", "banzhaf_iv"],
+                    help="value kind: Shapley (default) or Banzhaf values of the same game, or their interaction "
+                         "values (phi[F][F] per row, explained in consumer chunks)")
+    ap.add_argument("--iv-chunk", type=int, default=1 << 18, help="consumer rows per interaction-value launch")
     ap.add_argument("--pathdep", action="store_true",
                     help="path-dependent values from node covers (no background: the summary depends on the model "
                          "only, so a step is one explain)")
@@ -221,7 +224,7 @@ def main():
     n = X.shape[1]
     stream = torch.cuda.current_stream()
     tuning = None
-    if model.specialised and not args.no_autotune:
+    if model.specialised and not args.no_autotune and not args.values.endswith("_iv"):
         t0 = time.perf_counter()
         tuning = model.autotune(Bd, Xd)        # on the workload itself: the choice transfers exactly
         print(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {tuning}", file=sys.stderr, flush=True)
@@ -229,7 +232,9 @@ def main():
     # place from the (resident) background and explains every consumer row.
     # A path-dependent summary depends on the model only: it is built once and
     # a step is one explain.
-    values = wdf.BANZHAF if args.values == "banzhaf" else wdf.SHAPLEY
+    values = {"shapley": wdf.SHAPLEY, "banzhaf": wdf.BANZHAF, "shapley_iv": wdf.SHAPLEY_IV,
+              "banzhaf_iv": wdf.BANZHAF_IV}[args.values]
+    iv = values in (wdf.SHAPLEY_IV, wdf.BANZHAF_IV)
     summary_once_ms = None
     if args.pathdep:
         t0 = time.perf_counter()
@@ -238,7 +243,22 @@ def main():
         summary_once_ms = (time.perf_counter() - t0) * 1e3
     else:
         bg = wdf.Background(model, Bd, values=values)
-    if args.eager:
+    if iv:
+        # phi[F][F] per row: consumer chunks into one reused output buffer
+        F = ens.n_features
+        chunk = min(n, args.iv_chunk)
+        out_iv = torch.empty((F, F, chunk), dtype=torch.float32, device="cuda")
+        ws_iv = torch.empty(bg.iv_workspace_bytes(chunk), dtype=torch.uint8, device="cuda")
+        g_bg = wdf.Graph(bg, B=Bd)
+
+        def summarise():
+            g_bg.launch(stream)
+
+        def explain():
+            for a in range(0, n, chunk):
+                b = min(n, a + chunk)
+                bg.explain_iv(Xd[:, a:b], out=out_iv[:, :, :b - a], stream=stream, workspace=ws_iv)
+    elif args.eager:
         def summarise():
             if not args.pathdep:
                 bg.refresh(Bd, stream=stream)
@@ -279,14 +299,22 @@ def main():
     explain_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     value = n * args.steps / dt
 
-    ops_row = int(method_ops_per_row(ens))
-    achieved = ops_row * n / (explain_ms * 1e-3)
-    gather = tuning["gather"] if tuning else ("quads" if model.specialised else None)
-    traffic = measured_traffic(wdf, ens, args.workload, gather) if gather else None
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
-                "kernel": f"wdf_explain_{gather}" if gather else "k_explain_generic", "kernel_ms": explain_ms,
-                "ops_per_row": ops_row}
+    if iv:
+        # the interaction launches write F * F floats per row: HBM-bound by that output
+        out_bytes = 4.0 * ens.n_features ** 2 * n
+        achieved = out_bytes / (explain_ms * 1e-3)
+        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK, "traffic": None, "kernel": "k_explain_iv",
+                    "kernel_ms": explain_ms, "bytes_per_row": 4 * ens.n_features ** 2}
+    else:
+        ops_row = int(method_ops_per_row(ens))
+        achieved = ops_row * n / (explain_ms * 1e-3)
+        gather = tuning["gather"] if tuning else ("quads" if model.specialised else None)
+        traffic = measured_traffic(wdf, ens, args.workload, gather) if gather else None
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                    "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+                    "kernel": f"wdf_explain_{gather}" if gather else "k_explain_generic", "kernel_ms": explain_ms,
+                    "ops_per_row": ops_row}
     base = bg.base_value
     out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -306,7 +334,7 @@ def main():
         out["serving"] = serve_bench(wdf, ctx)
         sv = out["serving"]["loads"][0]["continuous_batching"]
         out["served_p50_ms"], out["served_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
-    if not args.no_cpu_baseline and not args.pathdep and args.values == "shapley":
+    if not args.no_cpu_baseline and not args.pathdep and args.values == "shapley":  # the headline method only
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ens, X[:, :64], B, args.cpu_seconds)
     print(json.dumps(out), flush=True)

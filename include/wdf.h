@@ -164,13 +164,18 @@ int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float 
  * Background game's interaction values are the per-cube formulas summed over
  * leaves and background rows, as for Shapley values, Section 7).  X: device
  * [F][ldx >= n]; iv: device [F * F][ldiv >= n], iv[(i * F + j) * ldiv + r]
- * for consumer r, symmetric in (i, j), diagonal 0.  Runs the generic
- * interaction kernel (per-lane LDS accumulators); needs F <= 640.
- * Asynchronous on hip_stream; allocates nothing.
- * Errors: INVALID_ARG (NULL, sizes, summary not of an interaction kind),
- * UNSUPPORTED (F > 640), DEVICE. */
+ * for consumer r, symmetric in (i, j), diagonal 0.  The rows' patterns of
+ * every group go to `workspace` (device memory of at least
+ * wdf_explain_iv_workspace(bg, n) bytes, owned by the caller, not shared by
+ * overlapping calls); then one wave per (64 rows, feature i) adds the pair
+ * tables into per-lane LDS accumulators.  Needs F <= 640.  Asynchronous on
+ * hip_stream; allocates nothing.
+ * Errors: INVALID_ARG (NULL, sizes, small workspace, summary not of an
+ * interaction kind), UNSUPPORTED (F > 640, more than 65535 groups), DEVICE. */
 int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
-                   void *hip_stream);
+                   void *workspace, size_t workspace_bytes, void *hip_stream);
+/* Workspace bytes wdf_explain_iv needs for n rows (one byte per group and row). */
+int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n);
 
 /* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
  * f(c) - base).  For a path-dependent summary: the cover-weighted mean.  After

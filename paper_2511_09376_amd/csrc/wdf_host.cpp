@@ -834,8 +834,13 @@ extern "C" int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t 
   return WDF_OK;
 }
 
+extern "C" int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n) {
+  if (!bg || n < 0) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv_workspace: NULL summary or n < 0");
+  return std::max<int64_t>((int64_t)bg->model->groups.size() * n, 1);
+}
+
 extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
-                              void *hip_stream) {
+                              void *workspace, size_t workspace_bytes, void *hip_stream) {
   if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: NULL summary");
   if (!bg->iv) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: not an interaction summary");
   if (n < 0 || ldx < n || ldiv < n) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: need 0 <= n <= ldx, ldiv");
@@ -844,10 +849,15 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
   wdf_model *M = bg->model;
   if (M->n_features > kMaxFeaturesIV)
     return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %d features exceeds %d", M->n_features, kMaxFeaturesIV);
+  const int64_t G = (int64_t)M->groups.size();
+  if (G > 65535) return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %lld groups exceeds 65535", (long long)G);
+  if (!workspace || (int64_t)workspace_bytes < G * n)
+    return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
+                     (long long)(G * n));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
-  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), M->d_iv_off.as<int64_t>(),
+  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_off.as<int64_t>(),
                             M->d_ivf_off.as<int32_t>(), M->d_iv_entries.as<int2>(), bg->d_tab.as<float>(), X, n, ldx,
-                            iv, ldiv, M->n_features, s));
+                            (uint8_t *)workspace, iv, ldiv, M->n_features, s));
   return WDF_OK;
 }
 

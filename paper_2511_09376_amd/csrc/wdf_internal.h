@@ -26,9 +26,10 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s);
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
                             const int64_t *s_class_off, const double *S, float *tab, hipStream_t s);
-hipError_t launch_explain_iv(const Group *groups, const PathNode *path, const int64_t *iv_off,
+// patterns of every group into pat (n_groups * n bytes), then the interaction kernel
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
                              const int32_t *feat_off, const int2 *entries, const float *tab, const float *X,
-                             int64_t n, int64_t ldx, float *out, int64_t ldo, int F, hipStream_t s);
+                             int64_t n, int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s);
 // largest feature count the interaction kernel's LDS accumulators hold (one wave)
 constexpr int kMaxFeaturesIV = 640;
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

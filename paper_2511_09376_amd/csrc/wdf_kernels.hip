@@ -422,21 +422,32 @@ __global__ __launch_bounds__(256) void k_expand_iv(const Group *__restrict__ gro
   }
 }
 
+// Patterns of every group for every row, one byte each (depth <= 8):
+// pat[g * n + r].  Computed once per call, read by every feature's wave.
+__global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ groups,
+                                                     const PathNode *__restrict__ path, const float *__restrict__ X,
+                                                     int64_t n, int64_t ldx, uint8_t *__restrict__ pat) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const int64_t gi = blockIdx.y;
+  pat[gi * n + r] = (uint8_t)group_pattern(groups[gi], path, X, ldx, r);
+}
+
 // Interaction values of consumer rows: one wave = 64 rows and one feature i
 // (blockIdx.y).  The wave walks the groups whose path carries i (first
-// occurrence, list [feat_off[i], feat_off[i+1]) of (group, position)), finds
+// occurrence, list [feat_off[i], feat_off[i+1]) of (group, position)), reads
 // each row's pattern and adds the pair tables into per-lane accumulators of
 // every other feature j of the path, kept in LDS ([wave][j][lane]: the lanes
-// of a wave add to one j at a time, 64 consecutive words).  Then row r's
+// of a wave add to one j at a time, 64 consecutive words; each lane adds to
+// its own words only, in program order).  Then row r's
 // iv[(i * F + j) * ldo + r] = acc[j] for all j (diagonal 0).
 __global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ groups,
                                                     const PathNode *__restrict__ path,
                                                     const int64_t *__restrict__ iv_off,
                                                     const int32_t *__restrict__ feat_off,
                                                     const int2 *__restrict__ entries,
-                                                    const float *__restrict__ tab, const float *__restrict__ X,
-                                                    int64_t n, int64_t ldx, float *__restrict__ out, int64_t ldo,
-                                                    int F) {
+                                                    const float *__restrict__ tab, const uint8_t *__restrict__ pat,
+                                                    int64_t n, float *__restrict__ out, int64_t ldo, int F) {
   extern __shared__ float acc_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   const int i = blockIdx.y;
@@ -446,20 +457,15 @@ __global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ gr
   for (int j = 0; j < F; ++j) acc[j * 64 + lane] = 0.f;
   for (int e = feat_off[i]; e < feat_off[i + 1]; ++e) {
     const int2 en = entries[e];
+    const uint32_t p = pat[(int64_t)en.x * n + rr];
     const Group g = groups[en.x];
     const PathNode *pn = path + g.path_off;
     const int d = g.depth, k1 = en.y;
-    uint32_t p = 0;
-    for (int k = 0; k < d; ++k) {
-      const float x = X[(int64_t)pn[k].feat * ldx + rr];
-      const bool left = x != x ? pn[k].dl != 0 : x < pn[k].thr;
-      p = 2u * p + (left == (pn[k].dir == 0) ? 1u : 0u);
-    }
     const float *T = tab + iv_off[en.x];
     for (int k2 = 0; k2 < d; ++k2) {
       if (k2 == k1 || !pn[k2].first) continue;
       const int q = k1 < k2 ? pair_index(k1, k2, d) : pair_index(k2, k1, d);
-      acc[pn[k2].feat * 64 + lane] += T[((int64_t)q << d) + p];
+      atomicAdd(&acc[pn[k2].feat * 64 + lane], T[((int64_t)q << d) + p]);
     }
   }
   if (row < n)
@@ -474,17 +480,23 @@ hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n
   return hipGetLastError();
 }
 
-hipError_t launch_explain_iv(const Group *groups, const PathNode *path, const int64_t *iv_off,
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
                              const int32_t *feat_off, const int2 *entries, const float *tab, const float *X,
-                             int64_t n, int64_t ldx, float *out, int64_t ldo, int F, hipStream_t s) {
+                             int64_t n, int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  if (n_groups > 0) {
+    hipLaunchKernelGGL(k_patterns_u8, dim3((unsigned)((n + 255) / 256), (unsigned)n_groups), dim3(256), 0, s, groups,
+                       path, X, n, ldx, pat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   int waves = (int)((160 * 1024) / ((int64_t)F * 64 * 4));
   waves = waves > 4 ? 4 : waves;
   if (waves < 1) return hipErrorInvalidValue;  // the caller checks F first
   const size_t lds = (size_t)waves * F * 64 * sizeof(float);
   const int64_t blocks = (n + 64 * waves - 1) / (64 * waves);
   hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F), dim3(64 * waves), lds, s, groups, path, iv_off,
-                     feat_off, entries, tab, X, n, ldx, out, ldo, F);
+                     feat_off, entries, tab, pat, n, out, ldo, F);
   return hipGetLastError();
 }
 

@@ -100,7 +100,7 @@ class Tuning(C.Structure):
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
-    "wdf_base_value", "wdf_explain_iv", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
+    "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
     "wdf_debug_specialised_source", "wdf_model_autotune", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
@@ -128,7 +128,9 @@ def lib():
         L.wdf_bg_destroy.argtypes = [P]
         L.wdf_explain.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_base_value.argtypes = [P, C.POINTER(C.c_double)]
-        L.wdf_explain_iv.argtypes = [P, P, I64, I64, P, I64, P]
+        L.wdf_explain_iv.argtypes = [P, P, I64, I64, P, I64, P, C.c_size_t, P]
+        L.wdf_explain_iv_workspace.argtypes = [P, I64]
+        L.wdf_explain_iv_workspace.restype = I64
         L.wdf_background_refresh.argtypes = [P, P, I64, P]
         L.wdf_graph_create.argtypes = [P, P, I64, P, I64, I64, P, I64, C.POINTER(P)]
         L.wdf_graph_launch.argtypes = [P, P]
@@ -331,10 +333,12 @@ class Background:
                                  _stream_handle(stream)))
         return out
 
-    def explain_iv(self, X, out=None, stream=None):
+    def explain_iv(self, X, out=None, stream=None, workspace=None):
         """Interaction values [n_features, n_features, n] (float32 CUDA tensor,
         symmetric, diagonal 0) of consumer rows X [n_features, n]; the summary
-        must have been loaded with SHAPLEY_IV or BANZHAF_IV."""
+        must have been loaded with SHAPLEY_IV or BANZHAF_IV.  `workspace`: a
+        uint8 CUDA tensor of at least iv_workspace_bytes(n) bytes (allocated
+        here when None)."""
         import torch
         F = self.model.n_features
         X = _colmajor_tensor(X, F, "X")
@@ -346,9 +350,15 @@ class Background:
             raise ValueError("out must be float32 [F, F, n] with rows contiguous")
         ldx = X.stride(0) if n else 0
         ldo = out.stride(1) if n else 0
+        need = self.iv_workspace_bytes(n)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
         _check(lib().wdf_explain_iv(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldo,
-                                    _stream_handle(stream)))
+                                    C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
         return out
+
+    def iv_workspace_bytes(self, n: int) -> int:
+        return int(_check(lib().wdf_explain_iv_workspace(self.h, n)))
 
     def refresh(self, B, stream=None):
         """Recompute the summary in place from new background rows B (CUDA

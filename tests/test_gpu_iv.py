@@ -110,3 +110,6 @@ def test_iv_refresh_and_refusals(wdf, ctx):
         wdf.Background(model, values=wdf.SHAPLEY_IV, pathdep=True)
     with pytest.raises(wdf.WdfError):
         wdf.Server(bg, 1 << 28, 256, queue_cap=4)
+    small = torch.empty(bg.iv_workspace_bytes(X.shape[1]) - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(wdf.WdfError):
+        bg.explain_iv(_cuda(X), workspace=small)
