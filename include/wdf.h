@@ -167,11 +167,11 @@ int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float 
  * for consumer r, symmetric in (i, j), diagonal 0.  The rows' patterns of
  * every group go to `workspace` (device memory of at least
  * wdf_explain_iv_workspace(bg, n) bytes, owned by the caller, not shared by
- * overlapping calls); then one wave per (64 rows, feature i) adds the pair
- * tables into per-lane LDS accumulators.  Needs F <= 640.  Asynchronous on
- * hip_stream; allocates nothing.
+ * overlapping calls); then one wave per (64 rows, feature i, slice of 32
+ * partner features j) adds the pair tables into per-lane LDS accumulators.
+ * Asynchronous on hip_stream; allocates nothing.
  * Errors: INVALID_ARG (NULL, sizes, small workspace, summary not of an
- * interaction kind), UNSUPPORTED (F > 640, more than 65535 groups), DEVICE. */
+ * interaction kind), UNSUPPORTED (more than 65535 groups), DEVICE. */
 int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
                    void *workspace, size_t workspace_bytes, void *hip_stream);
 /* Workspace bytes wdf_explain_iv needs for n rows (one byte per group and row). */

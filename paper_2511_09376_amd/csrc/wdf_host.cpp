@@ -847,8 +847,6 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
   if (n == 0) return WDF_OK;
   if (!X || !iv) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: NULL X or iv");
   wdf_model *M = bg->model;
-  if (M->n_features > kMaxFeaturesIV)
-    return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %d features exceeds %d", M->n_features, kMaxFeaturesIV);
   const int64_t G = (int64_t)M->groups.size();
   if (G > 65535) return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %lld groups exceeds 65535", (long long)G);
   if (!workspace || (int64_t)workspace_bytes < G * n)

@@ -433,28 +433,30 @@ __global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ g
   pat[gi * n + r] = (uint8_t)group_pattern(groups[gi], path, X, ldx, r);
 }
 
-// Interaction values of consumer rows: one wave = 64 rows and one feature i
-// (blockIdx.y).  The wave walks the groups whose path carries i (first
+// Interaction values of consumer rows: one wave = 64 rows, one feature i
+// (blockIdx.y) and one slice of partner features j in [j0, j0 + FS)
+// (blockIdx.z).  The wave walks the groups whose path carries i (first
 // occurrence, list [feat_off[i], feat_off[i+1]) of (group, position)), reads
-// each row's pattern and adds the pair tables into per-lane accumulators of
-// every other feature j of the path, kept in LDS ([wave][j][lane]: the lanes
-// of a wave add to one j at a time, 64 consecutive words; each lane adds to
-// its own words only, in program order).  Then row r's
-// iv[(i * F + j) * ldo + r] = acc[j] for all j (diagonal 0).
+// each row's pattern and adds the pair tables of the partners in its slice
+// into per-lane accumulators kept in LDS ([wave][j - j0][lane]: the lanes of a
+// wave add to one j at a time, 64 consecutive words; each lane adds to its own
+// words only, in program order).  Slicing j keeps the LDS per wave small, so
+// that more waves share a CU.  Then row r's iv[(i * F + j) * ldo + r] for j in
+// the slice (diagonal 0).
 __global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ groups,
                                                     const PathNode *__restrict__ path,
                                                     const int64_t *__restrict__ iv_off,
                                                     const int32_t *__restrict__ feat_off,
                                                     const int2 *__restrict__ entries,
                                                     const float *__restrict__ tab, const uint8_t *__restrict__ pat,
-                                                    int64_t n, float *__restrict__ out, int64_t ldo, int F) {
+                                                    int64_t n, float *__restrict__ out, int64_t ldo, int F, int FS) {
   extern __shared__ float acc_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
-  const int i = blockIdx.y;
+  const int i = blockIdx.y, j0 = blockIdx.z * FS, j1 = min(F, j0 + FS);
   const int64_t row = ((int64_t)blockIdx.x * waves + wave) * 64 + lane;
   const int64_t rr = row < n ? row : n - 1;
-  float *acc = acc_all + (int64_t)wave * F * 64;
-  for (int j = 0; j < F; ++j) acc[j * 64 + lane] = 0.f;
+  float *acc = acc_all + (int64_t)wave * FS * 64;
+  for (int j = 0; j < FS; ++j) acc[j * 64 + lane] = 0.f;
   for (int e = feat_off[i]; e < feat_off[i + 1]; ++e) {
     const int2 en = entries[e];
     const uint32_t p = pat[(int64_t)en.x * n + rr];
@@ -463,13 +465,14 @@ __global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ gr
     const int d = g.depth, k1 = en.y;
     const float *T = tab + iv_off[en.x];
     for (int k2 = 0; k2 < d; ++k2) {
-      if (k2 == k1 || !pn[k2].first) continue;
+      const int j = pn[k2].feat;
+      if (k2 == k1 || !pn[k2].first || j < j0 || j >= j1) continue;
       const int q = k1 < k2 ? pair_index(k1, k2, d) : pair_index(k2, k1, d);
-      atomicAdd(&acc[pn[k2].feat * 64 + lane], T[((int64_t)q << d) + p]);
+      atomicAdd(&acc[(j - j0) * 64 + lane], T[((int64_t)q << d) + p]);
     }
   }
   if (row < n)
-    for (int j = 0; j < F; ++j) out[((int64_t)i * F + j) * ldo + row] = acc[j * 64 + lane];
+    for (int j = j0; j < j1; ++j) out[((int64_t)i * F + j) * ldo + row] = acc[(j - j0) * 64 + lane];
 }
 
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
@@ -490,13 +493,14 @@ hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  int waves = (int)((160 * 1024) / ((int64_t)F * 64 * 4));
-  waves = waves > 4 ? 4 : waves;
-  if (waves < 1) return hipErrorInvalidValue;  // the caller checks F first
-  const size_t lds = (size_t)waves * F * 64 * sizeof(float);
+  // partner slices of at most 32 features: 8 KB of accumulators per wave,
+  // so LDS lets 16 or more waves share a CU
+  const int slices = (F + 31) / 32, FS = (F + slices - 1) / slices;
+  const int waves = 4;
+  const size_t lds = (size_t)waves * FS * 64 * sizeof(float);
   const int64_t blocks = (n + 64 * waves - 1) / (64 * waves);
-  hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F), dim3(64 * waves), lds, s, groups, path, iv_off,
-                     feat_off, entries, tab, pat, n, out, ldo, F);
+  hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F, (unsigned)slices), dim3(64 * waves), lds, s,
+                     groups, path, iv_off, feat_off, entries, tab, pat, n, out, ldo, F, FS);
   return hipGetLastError();
 }
 
