@@ -507,29 +507,49 @@ static int prepare_iv(wdf_model *M, int kind) {
       so += (int64_t)M->cls[dp].ncols * (dp * (dp - 1) / 2) << dp;
     }
     M->s_iv_total = so;
-    // per feature: (group, position) of every first occurrence on a path
+    // per feature i, one entry per first occurrence of i on a group's path:
+    // (group, offset and count of its partner list); a partner is (feature j
+    // at another first-occurrence position, offset of the pair table in the
+    // interaction tables)
     const int F = M->n_features;
-    std::vector<std::vector<int32_t>> lists((size_t)F);
+    if (M->iv_tab_size >= ((int64_t)1 << 31))
+      return set_error(WDF_E_UNSUPPORTED, "interaction tables of %lld floats exceed 2^31", (long long)M->iv_tab_size);
+    std::vector<std::vector<int32_t>> ent_of((size_t)F);
+    std::vector<int32_t> partners;
     for (size_t g = 0; g < G; ++g) {
       const Group &gr = M->groups[g];
-      for (int k = 0; k < gr.depth; ++k) {
-        const PathNode &pn = M->path[(size_t)gr.path_off + k];
-        if (!pn.first) continue;
-        lists[(size_t)pn.feat].push_back((int32_t)g);
-        lists[(size_t)pn.feat].push_back(k);
+      const int d = gr.depth;
+      for (int k1 = 0; k1 < d; ++k1) {
+        const PathNode &a = M->path[(size_t)gr.path_off + k1];
+        if (!a.first) continue;
+        const int32_t off = (int32_t)(partners.size() / 2);
+        int32_t cnt = 0;
+        for (int k2 = 0; k2 < d; ++k2) {
+          const PathNode &b = M->path[(size_t)gr.path_off + k2];
+          if (k2 == k1 || !b.first) continue;
+          const int u = std::min(k1, k2), v = std::max(k1, k2);
+          const int q = u * (2 * d - u - 1) / 2 + (v - u - 1);
+          partners.push_back(b.feat);
+          partners.push_back((int32_t)(M->iv_off[g] + ((int64_t)q << d)));
+          ++cnt;
+        }
+        auto &e = ent_of[(size_t)a.feat];
+        e.insert(e.end(), {(int32_t)g, off, cnt, 0});
       }
     }
     std::vector<int32_t> foff((size_t)F + 1, 0), ent;
     for (int f = 0; f < F; ++f) {
-      foff[(size_t)f + 1] = foff[(size_t)f] + (int32_t)(lists[(size_t)f].size() / 2);
-      ent.insert(ent.end(), lists[(size_t)f].begin(), lists[(size_t)f].end());
+      foff[(size_t)f + 1] = foff[(size_t)f] + (int32_t)(ent_of[(size_t)f].size() / 4);
+      ent.insert(ent.end(), ent_of[(size_t)f].begin(), ent_of[(size_t)f].end());
     }
-    if (ent.empty()) ent.assign(2, 0);
+    if (ent.empty()) ent.assign(4, 0);
+    if (partners.empty()) partners.assign(2, 0);
     std::vector<int64_t> soff(M->s_iv_class_off, M->s_iv_class_off + WDF_MAX_DEPTH + 1);
     if ((rc = upload(M->d_iv_off, M->iv_off.empty() ? std::vector<int64_t>(1, 0) : M->iv_off, s))) return rc;
     if ((rc = upload(M->d_siv_class_off, soff, s))) return rc;
     if ((rc = upload(M->d_ivf_off, foff, s))) return rc;
     if ((rc = upload(M->d_iv_entries, ent, s))) return rc;
+    if ((rc = upload(M->d_iv_partners, partners, s))) return rc;
     M->iv_layout = true;
   }
   if (!M->iv_coef_ready[kind]) {
@@ -853,8 +873,8 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
     return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
                      (long long)(G * n));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
-  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_off.as<int64_t>(),
-                            M->d_ivf_off.as<int32_t>(), M->d_iv_entries.as<int2>(), bg->d_tab.as<float>(), X, n, ldx,
+  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_ivf_off.as<int32_t>(),
+                            M->d_iv_entries.as<int4>(), M->d_iv_partners.as<int2>(), bg->d_tab.as<float>(), X, n, ldx,
                             (uint8_t *)workspace, iv, ldiv, M->n_features, s));
   return WDF_OK;
 }

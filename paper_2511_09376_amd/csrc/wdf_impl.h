@@ -125,12 +125,13 @@ struct wdf_model {
 
   // interaction values (prepared at the first summary of an interaction kind):
   // per group the offset of its pair tables, per class the offset of its
-  // products, per feature the (group, position) list of its first occurrences
+  // products, per feature the list of its first occurrences with their
+  // partner features and pair-table offsets
   bool iv_layout = false;
   std::vector<int64_t> iv_off;
   int64_t iv_tab_size = 0, s_iv_total = 0;
   int64_t s_iv_class_off[WDF_MAX_DEPTH + 1] = {};
-  wdf::DevBuf d_iv_off, d_siv_class_off, d_ivf_off, d_iv_entries;
+  wdf::DevBuf d_iv_off, d_siv_class_off, d_ivf_off, d_iv_entries, d_iv_partners;
   bool iv_coef_ready[2] = {false, false};
   wdf::DevBuf d_coef_iv[2][WDF_MAX_DEPTH + 1];  // [Shapley/Banzhaf][dprime]
 };

@@ -435,19 +435,19 @@ __global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ g
 
 // Interaction values of consumer rows: one wave = 64 rows, one feature i
 // (blockIdx.y) and one slice of partner features j in [j0, j0 + FS)
-// (blockIdx.z).  The wave walks the groups whose path carries i (first
-// occurrence, list [feat_off[i], feat_off[i+1]) of (group, position)), reads
-// each row's pattern and adds the pair tables of the partners in its slice
-// into per-lane accumulators kept in LDS ([wave][j - j0][lane]: the lanes of a
-// wave add to one j at a time, 64 consecutive words; each lane adds to its own
-// words only, in program order).  Slicing j keeps the LDS per wave small, so
-// that more waves share a CU.  Then row r's iv[(i * F + j) * ldo + r] for j in
-// the slice (diagonal 0).
-__global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ groups,
-                                                    const PathNode *__restrict__ path,
-                                                    const int64_t *__restrict__ iv_off,
-                                                    const int32_t *__restrict__ feat_off,
-                                                    const int2 *__restrict__ entries,
+// (blockIdx.z).  The wave walks the first occurrences of i on group paths
+// (entries [feat_off[i], feat_off[i+1]): group, partner-list offset and
+// count), reads each row's pattern of that group and adds, for every partner
+// (feature j, pair-table offset) in its slice, the table entry into per-lane
+// accumulators kept in LDS ([wave][j - j0][lane]: the lanes of a wave add to
+// one j at a time, 64 consecutive words; each lane adds to its own words only,
+// in program order).  The lists are uniform across the wave, so they are read
+// through the scalar cache.  Slicing j keeps the LDS per wave small, so that
+// more waves share a CU.  Then row r's iv[(i * F + j) * ldo + r] for j in the
+// slice (diagonal 0).
+__global__ __launch_bounds__(256) void k_explain_iv(const int32_t *__restrict__ feat_off,
+                                                    const int4 *__restrict__ entries,
+                                                    const int2 *__restrict__ partners,
                                                     const float *__restrict__ tab, const uint8_t *__restrict__ pat,
                                                     int64_t n, float *__restrict__ out, int64_t ldo, int F, int FS) {
   extern __shared__ float acc_all[];
@@ -457,18 +457,17 @@ __global__ __launch_bounds__(256) void k_explain_iv(const Group *__restrict__ gr
   const int64_t rr = row < n ? row : n - 1;
   float *acc = acc_all + (int64_t)wave * FS * 64;
   for (int j = 0; j < FS; ++j) acc[j * 64 + lane] = 0.f;
-  for (int e = feat_off[i]; e < feat_off[i + 1]; ++e) {
-    const int2 en = entries[e];
-    const uint32_t p = pat[(int64_t)en.x * n + rr];
-    const Group g = groups[en.x];
-    const PathNode *pn = path + g.path_off;
-    const int d = g.depth, k1 = en.y;
-    const float *T = tab + iv_off[en.x];
-    for (int k2 = 0; k2 < d; ++k2) {
-      const int j = pn[k2].feat;
-      if (k2 == k1 || !pn[k2].first || j < j0 || j >= j1) continue;
-      const int q = k1 < k2 ? pair_index(k1, k2, d) : pair_index(k2, k1, d);
-      atomicAdd(&acc[(j - j0) * 64 + lane], T[((int64_t)q << d) + p]);
+  const int e0 = feat_off[i], e1 = feat_off[i + 1];
+  // the next entry's pattern loads while this entry's partners are added
+  uint32_t p_next = e0 < e1 ? pat[(int64_t)entries[e0].x * n + rr] : 0u;
+  for (int e = e0; e < e1; ++e) {
+    const int4 en = entries[e];
+    const uint32_t p = p_next;
+    if (e + 1 < e1) p_next = pat[(int64_t)entries[e + 1].x * n + rr];
+    for (int t = 0; t < en.z; ++t) {
+      const int2 pr = partners[en.y + t];
+      if (pr.x < j0 || pr.x >= j1) continue;
+      atomicAdd(&acc[(pr.x - j0) * 64 + lane], tab[(int64_t)pr.y + p]);
     }
   }
   if (row < n)
@@ -483,9 +482,9 @@ hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n
   return hipGetLastError();
 }
 
-hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
-                             const int32_t *feat_off, const int2 *entries, const float *tab, const float *X,
-                             int64_t n, int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s) {
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *feat_off,
+                             const int4 *entries, const int2 *partners, const float *tab, const float *X, int64_t n,
+                             int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n_groups > 0) {
     hipLaunchKernelGGL(k_patterns_u8, dim3((unsigned)((n + 255) / 256), (unsigned)n_groups), dim3(256), 0, s, groups,
@@ -500,7 +499,7 @@ hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t 
   const size_t lds = (size_t)waves * FS * 64 * sizeof(float);
   const int64_t blocks = (n + 64 * waves - 1) / (64 * waves);
   hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F, (unsigned)slices), dim3(64 * waves), lds, s,
-                     groups, path, iv_off, feat_off, entries, tab, pat, n, out, ldo, F, FS);
+                     feat_off, entries, partners, tab, pat, n, out, ldo, F, FS);
   return hipGetLastError();
 }
 
