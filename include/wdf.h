@@ -219,6 +219,16 @@ int wdf_debug_patterns(const wdf_model *model, const float *X, int64_t n, int64_
 int64_t wdf_debug_histograms(const wdf_bg *bg, uint32_t *host_out, int64_t cap);
 int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap);
 
+/* The library's coefficient matrix for d' = dprime distinct path features
+ * (1..8) and a value kind, as built on the host (no device needed):
+ * WDF_SHAPLEY / WDF_BANZHAF: M[(k * 2^d' + pc) * 2^d' + pb], the value of the
+ * feature at position k for the cube of the pattern pair (pc, pb) (Section 5's
+ * four rules; position 0 is the patterns' most significant bit);
+ * WDF_SHAPLEY_IV / WDF_BANZHAF_IV: M[(q * 2^d' + pc) * 2^d' + pb] for the q-th
+ * position pair (u, v), u < v, in lexicographic order.  Returns the entry
+ * count; copies into out when cap allows.  For tests. */
+int64_t wdf_debug_coef_matrix(int dprime, int values, double *out, int64_t cap);
+
 /* Model-specialised kernels without a device: lay out the ensemble, write the
  * generated HIP source (returned in out, NUL-terminated, when cap is large
  * enough; the return value is the source length) and, with compile != 0, also

@@ -920,6 +920,25 @@ extern "C" int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t c
   return n;
 }
 
+extern "C" int64_t wdf_debug_coef_matrix(int dprime, int values, double *out, int64_t cap) {
+  if (dprime < 1 || dprime > WDF_MAX_DEPTH) return set_error(WDF_E_INVALID_ARG, "wdf_debug_coef_matrix: dprime %d", dprime);
+  if (values < WDF_SHAPLEY || values > WDF_BANZHAF_IV)
+    return set_error(WDF_E_INVALID_ARG, "wdf_debug_coef_matrix: value kind %d", values);
+  std::vector<double> M;
+  try {
+    if (values >= WDF_SHAPLEY_IV) {
+      if (dprime < 2) return 0;
+      build_iv_matrix(dprime, values - WDF_SHAPLEY_IV, M);
+    } else {
+      build_coef_matrix(dprime, values, M);
+    }
+  } catch (const std::bad_alloc &) {
+    return set_error(WDF_E_OOM, "wdf_debug_coef_matrix: out of host memory");
+  }
+  if (out && cap >= (int64_t)M.size()) std::memcpy(out, M.data(), M.size() * sizeof(double));
+  return (int64_t)M.size();
+}
+
 extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int do_compile, char *out,
                                                 int64_t cap) {
   if (!desc) return set_error(WDF_E_INVALID_ARG, "wdf_debug_specialised_source: NULL desc");

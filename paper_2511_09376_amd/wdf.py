@@ -102,7 +102,7 @@ EXPORTS = [
     "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
     "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
-    "wdf_debug_specialised_source", "wdf_model_autotune", "wdf_server_create",
+    "wdf_debug_specialised_source", "wdf_debug_coef_matrix", "wdf_model_autotune", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
 
@@ -142,6 +142,8 @@ def lib():
         L.wdf_debug_tables.restype = I64
         L.wdf_debug_specialised_source.argtypes = [P, I, I, P, I64]
         L.wdf_debug_specialised_source.restype = I64
+        L.wdf_debug_coef_matrix.argtypes = [I, I, P, I64]
+        L.wdf_debug_coef_matrix.restype = I64
         L.wdf_model_autotune.argtypes = [P, P, I64, I64, P, I64, I64, P, C.POINTER(Tuning)]
         L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
@@ -197,6 +199,16 @@ def specialised_source(ens, compile: bool = False, kernel: int = KERNEL_SPECIALI
     buf = C.create_string_buffer(n + 1)
     _check(lib().wdf_debug_specialised_source(C.byref(desc), kernel, 0, buf, n + 1))
     return buf.value.decode()
+
+
+def coef_matrix(dprime: int, values: int = SHAPLEY) -> np.ndarray:
+    """The host-built coefficient matrix [positions or position pairs][2^d'][2^d']
+    (float64; no GPU needed)."""
+    n = _check(lib().wdf_debug_coef_matrix(dprime, values, None, 0))
+    out = np.empty(n, np.float64)
+    _check(lib().wdf_debug_coef_matrix(dprime, values, out.ctypes.data_as(C.c_void_p), n))
+    P = 1 << dprime
+    return out.reshape(-1, P, P)
 
 
 class Context:

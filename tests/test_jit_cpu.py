@@ -1,9 +1,10 @@
-"""CPU checks of the model-specialised kernels: the generated source compiles
-for gfx950 with hipRTC (no GPU needed) for the pair and the quad gather, and
-the gather reads what the layout promises."""
+"""CPU checks of the host side (no GPU needed): the generated kernels compile
+for gfx950 with hipRTC for the pair and the quad gather and gather what the
+layout promises; the host-built coefficient matrices equal the oracle's."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2511_09376_amd import synth
@@ -56,3 +57,36 @@ def test_gather_counts_match_the_layout(wdf):
     # every feature of the model is written to phi
     for f in range(ens.n_features):
         assert f"phi[{f} * ldphi + row]" in pairs
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("values", ["shapley", "banzhaf", "shapley_iv", "banzhaf_iv"])
+def test_host_coefficient_matrices_match_the_oracle(wdf, d, values):
+    """The library's host-built matrices against the oracle: every pattern pair
+    that Alg. 2 maps to a cube, valued by the oracle's per-cube formulas (a
+    single-cube WDNF over the d distinct path features); every other pair is
+    0 (a position where neither row follows the path makes the cube false)."""
+    import oracle
+    kind = oracle.BANZHAF if values.startswith("banzhaf") else oracle.SHAPLEY
+    iv = values.endswith("_iv")
+    code = {"shapley": wdf.SHAPLEY, "banzhaf": wdf.BANZHAF, "shapley_iv": wdf.SHAPLEY_IV,
+            "banzhaf_iv": wdf.BANZHAF_IV}[values]
+    if iv and d < 2:
+        return
+    M = wdf.coef_matrix(d, code)
+    P = 1 << d
+    pairs = [(u, v) for u in range(d) for v in range(u + 1, d)]
+    expect = np.zeros((len(pairs) if iv else d, P, P))
+    pc, pb, pos, neg = oracle.map_patterns_to_cube(d)
+    for c, b, pm, nm in zip(pc, pb, pos, neg):
+        lits = [k + 1 for k in range(d) if (pm >> k) & 1] + [-(k + 1) for k in range(d) if (nm >> k) & 1]
+        if not lits:
+            continue
+        if iv:
+            vals = oracle.wdnf_iv_values([(1.0, lits)], d, kind)
+            for q, (u, v) in enumerate(pairs):
+                expect[q, c, b] = vals[u, v]
+        else:
+            vals = oracle.wdnf_values([(1.0, lits)], d, kind)
+            expect[:, c, b] = vals
+    np.testing.assert_allclose(M, expect, rtol=1e-12, atol=1e-15)
