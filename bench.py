@@ -64,8 +64,8 @@ def method_ops_per_row(ens) -> int:  # noqa: C901
 def measured_traffic(wdf, ens, workload, gather):
     """HBM bytes per explain launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), reported
-    only while the generated kernel source is the one the counters were
-    taken on; None otherwise."""
+    only while the generated explain-kernel source is the one the counters
+    were taken on; None otherwise."""
     path = os.path.join(ROOT, "profiles", f"explain_{gather}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -76,7 +76,8 @@ def measured_traffic(wdf, ens, workload, gather):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip()
     flags = wdf.KERNEL_SPECIALISED | (wdf.KERNEL_PAIRS if gather == "pairs" else 0)
-    sha = hashlib.sha1(wdf.specialised_source(ens, kernel=flags).encode()).hexdigest()
+    src = wdf.specialised_source(ens, kernel=flags)
+    sha = hashlib.sha1(src[src.index("#define EXPLAIN_NAME"):].encode()).hexdigest()
     if fields.get("source_sha1") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])

@@ -244,14 +244,16 @@ int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int
 typedef struct {
   int quads;                  /* chosen explain gather: 1 quad tables, 0 pair tables */
   int hist_rounds;            /* chosen histogram grid: blocks per CU over the launch */
+  int hist_threads;           /* chosen histogram block: 512, 768 or 1024 threads (at most the
+                                 launch bound the model's histogram kernel was compiled for) */
   float explain_ms[2];        /* explain time with [0] pair tables, [1] quad tables */
-  float hist_ms[9];           /* histogram time with hist_rounds = index (1..8) */
+  float hist_ms[3][9];        /* histogram time with [512, 768, 1024 threads][hist_rounds = 1..8] */
 } wdf_tuning;
 
 /* Measure the model's specialised kernels on the caller's data and keep the
  * fastest configuration for later calls: the explain gather (pair or quad
  * tables, a compile-time choice: each variant is generated and compiled once
- * and cached) and the histogram grid (a launch-time choice).  B [F][ldb] (m
+ * and cached) and the histogram grid and block size (launch-time choices).  B [F][ldb] (m
  * rows) and X [F][ldx] (n rows) are device pointers; a sample of a few hundred
  * thousand rows is enough.  Runs and synchronises on hip_stream.  No summary
  * of the model may exist during the call (summaries hold tables laid out for

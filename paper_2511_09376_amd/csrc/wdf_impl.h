@@ -38,7 +38,12 @@ struct DevBuf {
   T *as() const { return static_cast<T *>(ptr); }
 };
 
-struct JitModule;  // compiled model-specialised kernels (wdf_jit.cpp)
+struct JitPart;    // one compiled program of model-specialised kernels (wdf_jit.cpp)
+struct JitModule;  // the histogram and explain programs of a model (wdf_jit.cpp)
+
+// Largest histogram block the generated kernel can be compiled for (its
+// launch bound; a launch may use any multiple of 64 threads up to the bound).
+constexpr int kHistMaxThreads = 1024;
 
 // Layout of the model-specialised kernels (wdf_jit.cpp).
 struct JitPlan {
@@ -48,7 +53,9 @@ struct JitPlan {
   std::vector<float> thr;       // sorted distinct thresholds, feature after feature
   std::vector<int32_t> thr_off; // n_features + 1
   std::vector<int32_t> rank;    // per node: index of its threshold among its feature's
-  int nt_hist = 512, nt_explain = 512;
+  int hist_bound = kHistMaxThreads;     // launch bound the histogram kernel is compiled for
+  int hist_bound_cap = kHistMaxThreads; // lowered when the kernel spilled registers at a larger bound
+  int nt_hist = 0, nt_explain = 512;    // threads per block (histogram: a launch-time choice, 0 = the bound)
   int explain_bpc = 1;           // explain blocks per CU sharing the LDS (512 / bpc threads each)
   int hist_cap = 32768;         // uint32 counters per histogram chunk (LDS)
   int stage_floats_max = 40960; // table floats per explain stage (LDS, double-buffered; capped by what fits)
@@ -82,7 +89,7 @@ struct wdf_ctx {
   int n_cu = 0;
   hipStream_t stream = nullptr;
   std::mutex jit_mu;
-  std::map<std::string, std::shared_ptr<wdf::JitModule>> jit_cache;  // by generated source
+  std::map<std::string, std::shared_ptr<wdf::JitPart>> jit_cache;  // by generated source
 };
 
 struct wdf_model {

@@ -31,12 +31,17 @@
 
 namespace wdf {
 
-struct JitModule {
+struct JitPart {
   hipModule_t mod = nullptr;
-  hipFunction_t hist = nullptr, explain = nullptr;
-  ~JitModule() {
+  hipFunction_t fn = nullptr;
+  ~JitPart() {
     if (mod) (void)hipModuleUnload(mod);
   }
+};
+
+struct JitModule {
+  std::shared_ptr<JitPart> hist_part, explain_part;
+  hipFunction_t hist = nullptr, explain = nullptr;
 };
 
 namespace {
@@ -147,6 +152,13 @@ int make_plan(wdf_model *M) {
   // than the buffers hold are searched in global memory)
   const int64_t lds_floats = 160 * 1024 / 4;
   P.nt_explain = 512 / P.explain_bpc;
+  // histogram launch bound: 1024 threads leave 128 VGPRs, enough for two
+  // tiles of up to 32 words (current and prefetched) and the masks of paths
+  // of up to six positions; otherwise 512 (256 VGPRs)
+  int max_depth = 0;
+  for (const Group &g : M->groups) max_depth = std::max(max_depth, g.depth);
+  P.hist_bound = std::min(P.hist_bound_cap, max_depth <= 6 && P.words <= 32 ? kHistMaxThreads : 512);
+  if (P.nt_hist <= 0 || P.nt_hist > P.hist_bound) P.nt_hist = P.hist_bound;
   const int64_t room = lds_floats / P.explain_bpc / 2 / 4 * 4;
   P.stage_floats = (int)std::min<int64_t>(P.stage_floats_max, room);
   P.thr_in_lds = (int64_t)P.thr_pad.size() <= 2 * (int64_t)P.stage_floats;
@@ -359,6 +371,7 @@ std::vector<int> used_words(const wdf_model *M, const TreeIndex &ix, int64_t a, 
 // is 0; a popcount then gives that pattern's count for the 64 rows, added to
 // the LDS histogram without conflicts (every lane owns one bin).
 struct CountGen {
+  static constexpr int64_t kLdsHalf = 16384;  // 64 KiB of u32 histogram slots
   const wdf_model *M;
   const TreeIndex &ix;
   std::ostringstream &o;
@@ -389,7 +402,13 @@ struct CountGen {
       o << "{ const u32 " << c << " = __builtin_popcount(" << acc[j].lo << ") + __builtin_popcount(" << acc[j].hi
         << ");";
       if (d < 6) o << " if (lane < " << (1 << d) << "u)";
-      o << " atomicAdd(&lh[" << (off + 64 * (int64_t)j) << " + adr" << std::min(d, 6) << "], " << c << "); }\n";
+      // slots past the first 64 KiB index from hb*, so that the byte offset
+      // stays within the 16-bit offset field of ds_add
+      const int64_t slot = off + 64 * (int64_t)j;
+      if (slot >= kLdsHalf)
+        o << " atomicAdd(&lh[" << (slot - kLdsHalf) << " + hb" << std::min(d, 6) << "], " << c << "); }\n";
+      else
+        o << " atomicAdd(&lh[" << slot << " + adr" << std::min(d, 6) << "], " << c << "); }\n";
     }
   }
 
@@ -482,10 +501,11 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
   o << "typedef unsigned long long u64;\n"
     << "#define NDM(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n"
     << "#define NDMS(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n";
-  o << "extern \"C\" __global__ __launch_bounds__(" << P.nt_hist
+  o << "extern \"C\" __global__ __launch_bounds__(" << P.hist_bound
     << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 tiles_per_block, u32* __restrict__ hist, const u32* __restrict__ perm, int live) {\n"
     << "  __shared__ u32 lh[" << P.hist_cap << "];\n"
     << "  const u32 lane = threadIdx.x & 63u;\n"
+    << "  const int nw = blockDim.x >> 6;  // waves of the block (any multiple of 64 threads up to the bound)\n"
     << "  const i64 ntiles = (m + 63) >> 6;\n"
     << "  const i64 tb0 = (i64)blockIdx.x * tiles_per_block;\n"
     << "  i64 tb1 = tb0 + tiles_per_block; if (tb1 > ntiles) tb1 = ntiles;\n"
@@ -493,26 +513,56 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
   for (int l = 0; l < 6; ++l) o << "  const u32 E" << l << " = (lane >> " << l << ") & 1u ? 0u : ~0u;\n";
   for (int d = 1; d <= std::min(5, maxd); ++d) o << "  const u32 adr" << d << " = rev6 >> " << 6 - d << ";\n";
   o << "  const u32 adr6 = (rev6 >> 1) | ((rev6 & 1u) << 5);\n";
+  // Bases of the second 64 KiB of the histogram: opaque to the compiler,
+  // which would otherwise keep one base register per slot there.
+  if (P.hist_cap > CountGen::kLdsHalf) {
+    for (int d = 1; d <= 6; ++d) {
+      if (d <= 5 && d > maxd) continue;
+      o << "  u32 hb" << d << " = adr" << d << " + " << CountGen::kLdsHalf << "u; asm(\"\" : \"+v\"(hb" << d << "));\n";
+    }
+  }
   o << "  switch (blockIdx.y) {\n";
   for (size_t c = 0; c < P.hist_chunks.size(); ++c) {
     const int64_t a = P.hist_chunks[c].first, b = P.hist_chunks[c].second;
     const int64_t h0 = M->groups[(size_t)a].hist_off;
     const int64_t h1 = M->groups[(size_t)b - 1].hist_off + ((int64_t)1 << M->groups[(size_t)b - 1].depth);
     gen.h0 = h0;
+    // The words of a wave's next tile are loaded while it counts the current
+    // one (software pipelining; the last prefetch re-reads row m - 1).  The
+    // load pointer steps by ldc and is opaque to the compiler, which would
+    // otherwise hold one 64-bit base per word in scalar registers.
+    const std::vector<int> ws = used_words(M, ix, a, b);
+    auto load_words = [&](const char *dst, const char *row) {
+      o << "      { const __attribute__((address_space(1))) u32* p_ = (const __attribute__((address_space(1))) u32*)(codes + " << row << ");";
+      int prev = 0;
+      for (int w : ws) {
+        if (w != prev) o << " p_ += (i64)" << (w - prev) << " * ldc; asm(\"\" : \"+v\"(p_));";
+        prev = w;
+        o << " " << dst << w << " = *p_;";
+      }
+      o << " }\n";
+    };
     o << "  case " << c << ": {\n"
-      << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist << ") lh[i] = 0u;\n"
+      << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += blockDim.x) lh[i] = 0u;\n"
       << "    __syncthreads();\n"
-      << "    for (i64 t = tb0 + (threadIdx.x >> 6); t < tb1; t += " << P.nt_hist / 64 << ") {\n"
+      << "    i64 t = tb0 + (threadIdx.x >> 6);\n";
+    for (int w : ws) o << "    u32 w" << w << " = 0u, n" << w << ";\n";
+    o << "    if (t < tb1) {\n      const i64 r0 = t * 64 + lane;\n      const i64 rr0 = r0 < m ? r0 : m - 1;\n";
+    load_words("w", "rr0");
+    o << "    }\n"
+      << "    for (; t < tb1; t += nw) {\n"
       << "      const i64 row = t * 64 + lane;\n"
-      << "      const i64 rr = row < m ? row : m - 1;\n"
       << "      const u64 V = __ballot(row < m);\n"
-      << "      const u32 vl = (u32)V, vh = (u32)(V >> 32);\n";
-    for (int w : used_words(M, ix, a, b)) o << "      const u32 w" << w << " = codes[" << w << " * ldc + rr];\n";
+      << "      const u32 vl = (u32)V, vh = (u32)(V >> 32);\n"
+      << "      const i64 rn = row + 64 * nw;\n"
+      << "      const i64 rrn = rn < m ? rn : m - 1;\n";
+    load_words("n", "rrn");
     gen.range(a, b);
+    for (int w : ws) o << "      w" << w << " = n" << w << ";\n";
     o << "    }\n"
       << "    __syncthreads();\n"
-      << "    for (int i = threadIdx.x; i < " << (h1 - h0) << "; i += " << P.nt_hist
-      << ") { const u32 v = lh[i]; if (v) atomicAdd(&hist[perm[" << h0 << " + i]], v); }\n";
+      << "    for (int i = threadIdx.x; i < " << (h1 - h0)
+      << "; i += blockDim.x) { const u32 v = lh[i]; if (v) atomicAdd(&hist[perm[" << h0 << " + i]], v); }\n";
     for (int64_t g = a; g < b; ++g)
       if (M->groups[(size_t)g].depth == 0)
         o << "    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&hist[" << M->groups[(size_t)g].hist_off
@@ -711,14 +761,23 @@ int compile(const std::string &src, std::vector<char> &code) {
 
 }  // namespace
 
-int jit_source(wdf_model *M, bool do_compile, std::string &src) {
+int jit_sources(wdf_model *M, std::string &hist_src, std::string &explain_src) {
   int rc = make_plan(M);
   if (rc) return rc;
   const TreeIndex ix = index_tree_groups(M);
-  src = gen_hist(M, ix) + "\n" + gen_explain(M, ix).substr(std::strlen(kPreamble));
+  hist_src = gen_hist(M, ix);
+  explain_src = gen_explain(M, ix);
+  return WDF_OK;
+}
+
+int jit_source(wdf_model *M, bool do_compile, std::string &src) {
+  std::string h, x;
+  int rc = jit_sources(M, h, x);
+  if (rc) return rc;
+  src = h + "\n" + x.substr(std::strlen(kPreamble));
   if (do_compile) {
-    std::vector<char> code;
-    if ((rc = compile(src, code))) return rc;
+    std::vector<char> ch, cx;
+    if ((rc = compile(h, ch)) || (rc = compile(x, cx))) return rc;
   }
   return WDF_OK;
 }
@@ -726,33 +785,68 @@ int jit_source(wdf_model *M, bool do_compile, std::string &src) {
 // Limits beyond which the generated code would be too large to be worth it.
 static const int64_t kMaxSpecialisedNodes = 200000;
 
+namespace {
+
+std::shared_ptr<JitPart> cached_part(wdf_model *M, const std::string &src) {
+  std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
+  auto it = M->ctx->jit_cache.find(src);
+  return it == M->ctx->jit_cache.end() ? nullptr : it->second;
+}
+
+int load_part(wdf_model *M, const std::string &src, const std::vector<char> &code, const char *name,
+              std::shared_ptr<JitPart> &out) {
+  auto p = std::make_shared<JitPart>();
+  hipError_t e = hipModuleLoadData(&p->mod, code.data());
+  if (e != hipSuccess) return hip_error(e, "hipModuleLoadData");
+  if ((e = hipModuleGetFunction(&p->fn, p->mod, name)) != hipSuccess) return hip_error(e, "hipModuleGetFunction");
+  std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
+  M->ctx->jit_cache[src] = p;
+  out = p;
+  return WDF_OK;
+}
+
+// register spills of a loaded kernel (its private segment), 0 if unknown
+int spill_bytes(hipFunction_t fn) {
+  int local = 0;
+  if (hipFuncGetAttribute(&local, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn) != hipSuccess) return 0;
+  return local;
+}
+
+}  // namespace
+
 int jit_build(wdf_model *M) {
   if (M->n_nodes > kMaxSpecialisedNodes)
     return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %lld nodes exceeds %lld", (long long)M->n_nodes,
                      (long long)kMaxSpecialisedNodes);
-  std::string src;
-  int rc = jit_source(M, false, src);
+  std::string hsrc, xsrc;
+  int rc = jit_sources(M, hsrc, xsrc);
   if (rc) return rc;
-  std::shared_ptr<JitModule> mod;
+  auto mod = std::make_shared<JitModule>();
+  mod->hist_part = cached_part(M, hsrc);
+  mod->explain_part = cached_part(M, xsrc);
   {
-    std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
-    auto it = M->ctx->jit_cache.find(src);
-    if (it != M->ctx->jit_cache.end()) mod = it->second;
+    // two programs, cached apart: variants that differ in one part (the
+    // explain gather, the histogram bound) reuse the other
+    std::vector<char> ch, cx;
+    if (!mod->hist_part && (rc = compile(hsrc, ch))) return rc;
+    if (!mod->explain_part && (rc = compile(xsrc, cx))) return rc;
+    if (!mod->hist_part && (rc = load_part(M, hsrc, ch, "wdf_hist_spec", mod->hist_part))) return rc;
+    if (!mod->explain_part && (rc = load_part(M, xsrc, cx, explain_kernel_name(M->jp), mod->explain_part))) return rc;
   }
-  if (!mod) {
-    std::vector<char> code;
-    if ((rc = compile(src, code))) return rc;
-    auto m = std::make_shared<JitModule>();
-    hipError_t e = hipModuleLoadData(&m->mod, code.data());
-    if (e != hipSuccess) return hip_error(e, "hipModuleLoadData");
-    if ((e = hipModuleGetFunction(&m->hist, m->mod, "wdf_hist_spec")) != hipSuccess)
-      return hip_error(e, "hipModuleGetFunction(wdf_hist_spec)");
-    if ((e = hipModuleGetFunction(&m->explain, m->mod, explain_kernel_name(M->jp))) != hipSuccess)
-      return hip_error(e, "hipModuleGetFunction(explain)");
-    std::lock_guard<std::mutex> lock(M->ctx->jit_mu);
-    M->ctx->jit_cache[src] = m;
-    mod = m;
+  // A histogram kernel that spills registers at its launch bound is rebuilt
+  // once at 512 threads (256 VGPRs); the explain program is kept.
+  if (M->jp.hist_bound > 512 && spill_bytes(mod->hist_part->fn) > 0) {
+    M->jp.hist_bound_cap = 512;
+    if ((rc = jit_sources(M, hsrc, xsrc))) return rc;
+    mod->hist_part = cached_part(M, hsrc);
+    if (!mod->hist_part) {
+      std::vector<char> ch;
+      if ((rc = compile(hsrc, ch))) return rc;
+      if ((rc = load_part(M, hsrc, ch, "wdf_hist_spec", mod->hist_part))) return rc;
+    }
   }
+  mod->hist = mod->hist_part->fn;
+  mod->explain = mod->explain_part->fn;
   JitPlan &P = M->jp;
   hipStream_t s = M->ctx->stream;
   // per feature: (offset in the padded thresholds, search steps); 0 steps for unused features

@@ -55,33 +55,44 @@ extern "C" int wdf_model_autotune(wdf_model *M, const float *B, int64_t m, int64
   hipStream_t s = (hipStream_t)hip_stream;
   *out = wdf_tuning{};
   for (float &t : out->explain_ms) t = -1.f;
-  for (float &t : out->hist_ms) t = -1.f;
+  for (auto &row : out->hist_ms)
+    for (float &t : row) t = -1.f;
   const int reps = 3;
   int rc = WDF_OK;
 
-  // histogram grid: a launch-time choice, timed on one histogram buffer
+  // histogram grid and block size: launch-time choices, timed on one
+  // histogram buffer
   {
     DevBuf hist, codes;
     if ((rc = hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(uint32_t)))) return rc;
     if ((rc = codes.alloc((size_t)M->jp.words * (size_t)m * sizeof(uint32_t)))) return rc;
-    const int keep = M->jp.hist_rounds;
-    int best = keep;
+    const int keep_r = M->jp.hist_rounds, keep_t = M->jp.nt_hist;
+    int best_r = keep_r, best_t = keep_t;
     float best_ms = -1.f;
-    for (int r : {1, 2, 3, 4, 6, 8}) {
-      M->jp.hist_rounds = r;
-      const float ms = time_runs(s, reps, [&] {
-        HIP_TRY(launch_fill_u32(hist.as<uint32_t>(), std::max<int64_t>(M->hist_size, 1), 0u, s));
-        return jit_hist(M, B, m, ldb, hist.as<uint32_t>(), codes.as<uint32_t>(), s);
-      }, rc);
-      if (rc) {
-        M->jp.hist_rounds = keep;
-        return rc;
+    const int threads[3] = {512, 768, 1024};
+    static_assert(kHistMaxThreads == 1024, "the sweep covers blocks up to the largest launch bound");
+    for (int ti = 0; ti < 3; ++ti) {
+      if (threads[ti] > M->jp.hist_bound) continue;  // beyond the compiled launch bound
+      for (int r : {1, 2, 3, 4, 6, 8}) {
+        M->jp.nt_hist = threads[ti];
+        M->jp.hist_rounds = r;
+        const float ms = time_runs(s, reps, [&] {
+          HIP_TRY(launch_fill_u32(hist.as<uint32_t>(), std::max<int64_t>(M->hist_size, 1), 0u, s));
+          return jit_hist(M, B, m, ldb, hist.as<uint32_t>(), codes.as<uint32_t>(), s);
+        }, rc);
+        if (rc) {
+          M->jp.hist_rounds = keep_r;
+          M->jp.nt_hist = keep_t;
+          return rc;
+        }
+        out->hist_ms[ti][r] = ms;
+        if (best_ms < 0.f || ms < best_ms) best_ms = ms, best_r = r, best_t = threads[ti];
       }
-      out->hist_ms[r] = ms;
-      if (best_ms < 0.f || ms < best_ms) best_ms = ms, best = r;
     }
-    M->jp.hist_rounds = best;
-    out->hist_rounds = best;
+    M->jp.hist_rounds = best_r;
+    M->jp.nt_hist = best_t;
+    out->hist_rounds = best_r;
+    out->hist_threads = best_t;
   }
 
   // explain gather: a compile-time choice; each variant gets a summary of B

@@ -93,8 +93,8 @@ def _finalizing() -> bool:
 
 
 class Tuning(C.Structure):
-    _fields_ = [("quads", C.c_int), ("hist_rounds", C.c_int), ("explain_ms", C.c_float * 2),
-                ("hist_ms", C.c_float * 9)]
+    _fields_ = [("quads", C.c_int), ("hist_rounds", C.c_int), ("hist_threads", C.c_int),
+                ("explain_ms", C.c_float * 2), ("hist_ms", (C.c_float * 9) * 3)]
 
 
 EXPORTS = [
@@ -260,8 +260,10 @@ class Model:
                                         C.c_void_p(X.data_ptr()), X.shape[1], X.stride(0), _stream_handle(stream),
                                         C.byref(t)))
         return {"gather": "quads" if t.quads else "pairs", "hist_rounds": int(t.hist_rounds),
+                "hist_threads": int(t.hist_threads),
                 "explain_ms": {"pairs": float(t.explain_ms[0]), "quads": float(t.explain_ms[1])},
-                "hist_ms": {str(r): float(t.hist_ms[r]) for r in range(1, 9) if t.hist_ms[r] >= 0}}
+                "hist_ms": {f"{nt}x{r}": float(t.hist_ms[i][r]) for i, nt in enumerate((512, 768, 1024))
+                            for r in range(1, 9) if t.hist_ms[i][r] >= 0}}
 
     def groups(self) -> dict:
         G = _check(lib().wdf_model_groups(self.h, None, None, None, None, None, None))

@@ -39,8 +39,10 @@ def test_autotune_then_parity(wdf, ctx, workload):
     assert rep["explain_ms"]["pairs"] > 0 and rep["explain_ms"]["quads"] > 0
     best = min(rep["explain_ms"], key=rep["explain_ms"].get)
     assert rep["gather"] == best
-    assert set(rep["hist_ms"]) == {"1", "2", "3", "4", "6", "8"}
-    assert rep["hist_rounds"] == int(min(rep["hist_ms"], key=rep["hist_ms"].get))
+    swept = {f"{nt}x{r}" for nt in (512, 768, 1024) for r in (1, 2, 3, 4, 6, 8)}
+    assert {f"512x{r}" for r in (1, 2, 3, 4, 6, 8)} <= set(rep["hist_ms"]) <= swept
+    fastest = min(rep["hist_ms"], key=rep["hist_ms"].get)
+    assert (rep["hist_threads"], rep["hist_rounds"]) == tuple(int(v) for v in fastest.split("x"))
     assert model.specialised
     bg = wdf.Background(model, Bd)
     phi = bg.explain(Xd).cpu().numpy()
