@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -507,49 +508,48 @@ static int prepare_iv(wdf_model *M, int kind) {
       so += (int64_t)M->cls[dp].ncols * (dp * (dp - 1) / 2) << dp;
     }
     M->s_iv_total = so;
-    // per feature i, one entry per first occurrence of i on a group's path:
-    // (group, offset and count of its partner list); a partner is (feature j
-    // at another first-occurrence position, offset of the pair table in the
-    // interaction tables)
+    // Work lists of the interaction kernel, one per feature i: for every
+    // group where i and another feature j both have a first occurrence on the
+    // path, one item (offset of the pair table of (i, j) in the interaction
+    // tables, group << 16 | j), sorted by j, then group.  Each list is padded
+    // to a multiple of 8 items with items of its last j that read the zero
+    // block after the tables.
     const int F = M->n_features;
-    if (M->iv_tab_size >= ((int64_t)1 << 31))
+    if (M->iv_tab_size + 256 >= ((int64_t)1 << 31))
       return set_error(WDF_E_UNSUPPORTED, "interaction tables of %lld floats exceed 2^31", (long long)M->iv_tab_size);
-    std::vector<std::vector<int32_t>> ent_of((size_t)F);
-    std::vector<int32_t> partners;
+    if (G > 65535 || F > 65535)
+      return set_error(WDF_E_UNSUPPORTED, "interaction values: %zu groups or %d features exceed 65535", G, F);
+    std::vector<std::vector<std::array<int32_t, 3>>> lists((size_t)F);  // (j, group, table offset)
     for (size_t g = 0; g < G; ++g) {
       const Group &gr = M->groups[g];
       const int d = gr.depth;
       for (int k1 = 0; k1 < d; ++k1) {
         const PathNode &a = M->path[(size_t)gr.path_off + k1];
         if (!a.first) continue;
-        const int32_t off = (int32_t)(partners.size() / 2);
-        int32_t cnt = 0;
         for (int k2 = 0; k2 < d; ++k2) {
           const PathNode &b = M->path[(size_t)gr.path_off + k2];
           if (k2 == k1 || !b.first) continue;
           const int u = std::min(k1, k2), v = std::max(k1, k2);
           const int q = u * (2 * d - u - 1) / 2 + (v - u - 1);
-          partners.push_back(b.feat);
-          partners.push_back((int32_t)(M->iv_off[g] + ((int64_t)q << d)));
-          ++cnt;
+          lists[(size_t)a.feat].push_back({b.feat, (int32_t)g, (int32_t)(M->iv_off[g] + ((int64_t)q << d))});
         }
-        auto &e = ent_of[(size_t)a.feat];
-        e.insert(e.end(), {(int32_t)g, off, cnt, 0});
       }
     }
-    std::vector<int32_t> foff((size_t)F + 1, 0), ent;
+    std::vector<int32_t> ioff((size_t)F + 1, 0), items;
     for (int f = 0; f < F; ++f) {
-      foff[(size_t)f + 1] = foff[(size_t)f] + (int32_t)(ent_of[(size_t)f].size() / 4);
-      ent.insert(ent.end(), ent_of[(size_t)f].begin(), ent_of[(size_t)f].end());
+      auto &l = lists[(size_t)f];
+      std::sort(l.begin(), l.end());
+      for (const auto &e : l) items.insert(items.end(), {e[2], (int32_t)((uint32_t)e[1] << 16 | (uint32_t)e[0])});
+      if (!l.empty())
+        while ((items.size() / 2) % 8) items.insert(items.end(), {(int32_t)M->iv_tab_size, l.back()[0]});
+      ioff[(size_t)f + 1] = (int32_t)(items.size() / 2);
     }
-    if (ent.empty()) ent.assign(4, 0);
-    if (partners.empty()) partners.assign(2, 0);
+    if (items.empty()) items.assign(2, 0);
     std::vector<int64_t> soff(M->s_iv_class_off, M->s_iv_class_off + WDF_MAX_DEPTH + 1);
     if ((rc = upload(M->d_iv_off, M->iv_off.empty() ? std::vector<int64_t>(1, 0) : M->iv_off, s))) return rc;
     if ((rc = upload(M->d_siv_class_off, soff, s))) return rc;
-    if ((rc = upload(M->d_ivf_off, foff, s))) return rc;
-    if ((rc = upload(M->d_iv_entries, ent, s))) return rc;
-    if ((rc = upload(M->d_iv_partners, partners, s))) return rc;
+    if ((rc = upload(M->d_iv_item_off, ioff, s))) return rc;
+    if ((rc = upload(M->d_iv_items, items, s))) return rc;
     M->iv_layout = true;
   }
   if (!M->iv_coef_ready[kind]) {
@@ -564,11 +564,12 @@ static int prepare_iv(wdf_model *M, int kind) {
   return WDF_OK;
 }
 
-// Table storage of a summary, zeroed once (the padding between tables is never
+// Table storage of a summary, zeroed once (the padding between tables, and the
+// 256 floats after the interaction tables that padding items read, are never
 // written again).
 static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
   int rc;
-  const int64_t n = bg->iv ? M->iv_tab_size : M->tab_size;
+  const int64_t n = bg->iv ? M->iv_tab_size + 256 : M->tab_size;
   if ((rc = bg->d_tab.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(float)))) return rc;
   HIP_TRY(hipMemsetAsync(bg->d_tab.ptr, 0, bg->d_tab.bytes, s));
   if (M->jit && !bg->iv) {
@@ -873,9 +874,9 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
     return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
                      (long long)(G * n));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
-  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_ivf_off.as<int32_t>(),
-                            M->d_iv_entries.as<int4>(), M->d_iv_partners.as<int2>(), bg->d_tab.as<float>(), X, n, ldx,
-                            (uint8_t *)workspace, iv, ldiv, M->n_features, s));
+  HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_item_off.as<int32_t>(),
+                            M->d_iv_items.as<int2>(), bg->d_tab.as<float>(), X, n, ldx, (uint8_t *)workspace, iv, ldiv,
+                            M->n_features, s));
   return WDF_OK;
 }
 

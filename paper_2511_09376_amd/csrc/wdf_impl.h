@@ -138,7 +138,7 @@ struct wdf_model {
   std::vector<int64_t> iv_off;
   int64_t iv_tab_size = 0, s_iv_total = 0;
   int64_t s_iv_class_off[WDF_MAX_DEPTH + 1] = {};
-  wdf::DevBuf d_iv_off, d_siv_class_off, d_ivf_off, d_iv_entries, d_iv_partners;
+  wdf::DevBuf d_iv_off, d_siv_class_off, d_iv_item_off, d_iv_items;
   bool iv_coef_ready[2] = {false, false};
   wdf::DevBuf d_coef_iv[2][WDF_MAX_DEPTH + 1];  // [Shapley/Banzhaf][dprime]
 };

@@ -27,9 +27,9 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
                             const int64_t *s_class_off, const double *S, float *tab, hipStream_t s);
 // patterns of every group into pat (n_groups * n bytes), then the interaction kernel
-hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *feat_off,
-                             const int4 *entries, const int2 *partners, const float *tab, const float *X, int64_t n,
-                             int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s);
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *item_off,
+                             const int2 *items, const float *tab, const float *X, int64_t n, int64_t ldx, uint8_t *pat,
+                             float *out, int64_t ldo, int F, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_xtab(const XUnit *units, int64_t n_units, const float *tab, float *xtab, hipStream_t s);
 

@@ -433,45 +433,74 @@ __global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ g
   pat[gi * n + r] = (uint8_t)group_pattern(groups[gi], path, X, ldx, r);
 }
 
-// Interaction values of consumer rows: one wave = 64 rows, one feature i
-// (blockIdx.y) and one slice of partner features j in [j0, j0 + FS)
-// (blockIdx.z).  The wave walks the first occurrences of i on group paths
-// (entries [feat_off[i], feat_off[i+1]): group, partner-list offset and
-// count), reads each row's pattern of that group and adds, for every partner
-// (feature j, pair-table offset) in its slice, the table entry into per-lane
-// accumulators kept in LDS ([wave][j - j0][lane]: the lanes of a wave add to
-// one j at a time, 64 consecutive words; each lane adds to its own words only,
-// in program order).  The lists are uniform across the wave, so they are read
-// through the scalar cache.  Slicing j keeps the LDS per wave small, so that
-// more waves share a CU.  Then row r's iv[(i * F + j) * ldo + r] for j in the
-// slice (diagonal 0).
-__global__ __launch_bounds__(256) void k_explain_iv(const int32_t *__restrict__ feat_off,
-                                                    const int4 *__restrict__ entries,
-                                                    const int2 *__restrict__ partners,
+// Interaction values of consumer rows: one wave = 64 rows and one feature i
+// (blockIdx.y).  The wave walks the work list of i: items (offset of the pair
+// table of (i, j) for one group, group << 16 | j), sorted by j, a multiple of
+// 8 of them.  Eight items at a time: the rows' patterns of the eight groups
+// (loaded while the previous eight are summed), then the eight table entries.
+// A register sums the entries of one j (a run of the sorted list); when j
+// changes, the sum is stored to iv[(i * F + j) * ldo + r] and the columns that
+// have no items (the diagonal among them) get 0.  The lists are uniform
+// across the wave, so they are read through the scalar cache, and j is a
+// scalar: the run tests are branches of the wave, not of lanes.
+__global__ __launch_bounds__(256) void k_explain_iv(const int32_t *__restrict__ item_off,
+                                                    const int2 *__restrict__ items,
                                                     const float *__restrict__ tab, const uint8_t *__restrict__ pat,
-                                                    int64_t n, float *__restrict__ out, int64_t ldo, int F, int FS) {
-  extern __shared__ float acc_all[];
+                                                    int64_t n, float *__restrict__ out, int64_t ldo, int F) {
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
-  const int i = blockIdx.y, j0 = blockIdx.z * FS, j1 = min(F, j0 + FS);
+  const int i = blockIdx.y;
   const int64_t row = ((int64_t)blockIdx.x * waves + wave) * 64 + lane;
   const int64_t rr = row < n ? row : n - 1;
-  float *acc = acc_all + (int64_t)wave * FS * 64;
-  for (int j = 0; j < FS; ++j) acc[j * 64 + lane] = 0.f;
-  const int e0 = feat_off[i], e1 = feat_off[i + 1];
-  // the next entry's pattern loads while this entry's partners are added
-  uint32_t p_next = e0 < e1 ? pat[(int64_t)entries[e0].x * n + rr] : 0u;
-  for (int e = e0; e < e1; ++e) {
-    const int4 en = entries[e];
-    const uint32_t p = p_next;
-    if (e + 1 < e1) p_next = pat[(int64_t)entries[e + 1].x * n + rr];
-    for (int t = 0; t < en.z; ++t) {
-      const int2 pr = partners[en.y + t];
-      if (pr.x < j0 || pr.x >= j1) continue;
-      atomicAdd(&acc[(pr.x - j0) * 64 + lane], tab[(int64_t)pr.y + p]);
+  const bool live = row < n;
+  float *o = out + (int64_t)i * F * ldo + row;
+  const int k0 = item_off[i], nch = (item_off[i + 1] - k0) / U;
+  int2 it[U];
+  uint32_t p[U];
+  if (nch) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) it[u] = items[k0 + u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = pat[(int64_t)((uint32_t)it[u].y >> 16) * n + rr];
+  }
+  int cur = 0;  // first column not yet stored
+  int rj = -1;  // column of the current run
+  float run = 0.f;
+  for (int c = 0; c < nch; ++c) {
+    float v[U];
+    int jv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = tab[(int64_t)it[u].x + p[u]];
+      jv[u] = it[u].y & 0xffff;
+    }
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) it[u] = items[k0 + (c + 1) * U + u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) p[u] = pat[(int64_t)((uint32_t)it[u].y >> 16) * n + rr];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (jv[u] != rj) {
+        if (rj >= 0) {
+          if (live) o[(int64_t)rj * ldo] = run;
+          cur = rj + 1;
+        }
+        for (; cur < jv[u]; ++cur)
+          if (live) o[(int64_t)cur * ldo] = 0.f;
+        rj = jv[u];
+        run = 0.f;
+      }
+      run += v[u];
     }
   }
-  if (row < n)
-    for (int j = j0; j < j1; ++j) out[((int64_t)i * F + j) * ldo + row] = acc[(j - j0) * 64 + lane];
+  if (rj >= 0) {
+    if (live) o[(int64_t)rj * ldo] = run;
+    cur = rj + 1;
+  }
+  for (; cur < F; ++cur)
+    if (live) o[(int64_t)cur * ldo] = 0.f;
 }
 
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
@@ -482,9 +511,9 @@ hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n
   return hipGetLastError();
 }
 
-hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *feat_off,
-                             const int4 *entries, const int2 *partners, const float *tab, const float *X, int64_t n,
-                             int64_t ldx, uint8_t *pat, float *out, int64_t ldo, int F, hipStream_t s) {
+hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *item_off,
+                             const int2 *items, const float *tab, const float *X, int64_t n, int64_t ldx, uint8_t *pat,
+                             float *out, int64_t ldo, int F, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n_groups > 0) {
     hipLaunchKernelGGL(k_patterns_u8, dim3((unsigned)((n + 255) / 256), (unsigned)n_groups), dim3(256), 0, s, groups,
@@ -492,14 +521,10 @@ hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  // partner slices of at most 32 features: 8 KB of accumulators per wave,
-  // so LDS lets 16 or more waves share a CU
-  const int slices = (F + 31) / 32, FS = (F + slices - 1) / slices;
   const int waves = 4;
-  const size_t lds = (size_t)waves * FS * 64 * sizeof(float);
   const int64_t blocks = (n + 64 * waves - 1) / (64 * waves);
-  hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F, (unsigned)slices), dim3(64 * waves), lds, s,
-                     feat_off, entries, partners, tab, pat, n, out, ldo, F, FS);
+  hipLaunchKernelGGL(k_explain_iv, dim3((unsigned)blocks, (unsigned)F), dim3(64 * waves), 0, s, item_off, items, tab,
+                     pat, n, out, ldo, F);
   return hipGetLastError();
 }
 
