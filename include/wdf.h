@@ -149,6 +149,12 @@ int wdf_pathdep_load(wdf_model *model, int values, void *hip_stream, wdf_bg **ou
 
 void wdf_bg_destroy(wdf_bg *bg);
 
+/* 1 when the summary is explained by model-specialised kernels (Shapley and
+ * Banzhaf values: the model's; interaction values: the model's interaction
+ * kernels, which very large models do without), 0 for the generic ones or a
+ * NULL summary. */
+int wdf_bg_specialised(const wdf_bg *bg);
+
 /* phi[f * ldphi + r] = value of feature f for consumer row r, r < n.  X and phi
  * are device pointers (column-major), n >= 0, ldx >= n, ldphi >= n.  Every
  * feature row of phi in [0, n_features) is written (exact 0.0 for features no
@@ -236,6 +242,14 @@ int64_t wdf_debug_coef_matrix(int dprime, int values, double *out, int64_t cap);
  * wdf_last_error()).  `kernel` takes the flags of wdf_model_load (only
  * WDF_KERNEL_PAIRS matters here).  For tools and tests; needs no GPU. */
 int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int compile, char *out, int64_t cap);
+
+/* Generated source of the model's specialised interaction-value kernel
+ * (wdf_explain_iv on a summary of a model with specialised kernels; it adds
+ * the pair tables of Table table_shap_iv / Formula
+ * banzhaf_simplified_formula_interactions, laid out per (group, feature) and
+ * interleaved by pattern).  Same buffer convention as
+ * wdf_debug_specialised_source; needs no GPU. */
+int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, int64_t cap);
 
 /* ---- autotuning --------------------------------------------------------- */
 

@@ -53,4 +53,20 @@ inline int64_t xunit_floats(const XUnit &u) {
   return 4 * (int64_t)((u.nv + 3) / 4) * ((int64_t)1 << (u.depth + u.quad));
 }
 
+// A unit of the specialised interaction tables: one group and one feature i
+// at its first path position; the pair tables of i with the other first
+// positions (partners, in path order) interleaved by pattern:
+// [plane][pattern][4 partners], zeros after the last partner.
+struct IvUnit {
+  int64_t src;     // the group's pair tables (interaction-table offset)
+  int64_t dst;     // offset in the interleaved tables (floats, multiple of 4)
+  int32_t depth;   // path positions of the group
+  int32_t cnt;     // partners, 1..7
+  int32_t q[7];    // pair index of (i, partner s) among the group's position pairs
+  int32_t group;   // the group
+};
+
+// floats of a unit in the interleaved interaction tables
+inline int64_t ivunit_floats(const IvUnit &u) { return 4 * (int64_t)((u.cnt + 3) / 4) << u.depth; }
+
 }  // namespace wdf

@@ -463,6 +463,11 @@ extern "C" void wdf_model_destroy(wdf_model *model) {
 
 extern "C" int wdf_model_specialised(const wdf_model *model) { return (model && model->jit) ? 1 : 0; }
 
+extern "C" int wdf_bg_specialised(const wdf_bg *bg) {
+  if (!bg) return 0;
+  return (bg->iv ? bg->iv_spec : bg->model->jit != nullptr) ? 1 : 0;
+}
+
 extern "C" int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32_t *depth, int64_t *leaf_left,
                                     int64_t *leaf_right, int64_t *hist_offset, int64_t *table_offset) {
   if (!model) return set_error(WDF_E_INVALID_ARG, "wdf_model_groups: NULL model");
@@ -489,62 +494,116 @@ static hipStream_t pick_stream(wdf_ctx *, void *s) { return (hipStream_t)s; }
 
 // Interaction layout and coefficient matrices, prepared once per model and
 // kind (the caller holds the model's workspace lock).
+// Host side of the interaction layout: table offsets, the generic kernel's
+// work lists (ioff, items) and the specialised kernel's units.  Needs no GPU.
+static int iv_layout_host(wdf_model *M, std::vector<int32_t> &ioff, std::vector<int32_t> &items) {
+  const size_t G = M->groups.size();
+  M->iv_off.assign(G, 0);
+  int64_t off = 0;
+  for (size_t g = 0; g < G; ++g) {
+    const int d = M->groups[g].depth;
+    M->iv_off[g] = off;
+    off += ((((int64_t)d * (d - 1) / 2) << d) + 3) & ~(int64_t)3;
+  }
+  M->iv_tab_size = off;
+  int64_t so = 0;
+  for (int dp = 0; dp <= WDF_MAX_DEPTH; ++dp) {
+    M->s_iv_class_off[dp] = so;
+    so += (int64_t)M->cls[dp].ncols * (dp * (dp - 1) / 2) << dp;
+  }
+  M->s_iv_total = so;
+  // Work lists of the interaction kernel, one per feature i: for every
+  // group where i and another feature j both have a first occurrence on the
+  // path, one item (offset of the pair table of (i, j) in the interaction
+  // tables, group << 16 | j), sorted by j, then group.  Each list is padded
+  // to a multiple of 8 items with items of its last j that read the zero
+  // block after the tables.
+  const int F = M->n_features;
+  if (M->iv_tab_size + 256 >= ((int64_t)1 << 31))
+    return set_error(WDF_E_UNSUPPORTED, "interaction tables of %lld floats exceed 2^31", (long long)M->iv_tab_size);
+  if (G > 65535 || F > 65535)
+    return set_error(WDF_E_UNSUPPORTED, "interaction values: %zu groups or %d features exceed 65535", G, F);
+  std::vector<std::vector<std::array<int32_t, 3>>> lists((size_t)F);  // (j, group, table offset)
+  for (size_t g = 0; g < G; ++g) {
+    const Group &gr = M->groups[g];
+    const int d = gr.depth;
+    for (int k1 = 0; k1 < d; ++k1) {
+      const PathNode &a = M->path[(size_t)gr.path_off + k1];
+      if (!a.first) continue;
+      for (int k2 = 0; k2 < d; ++k2) {
+        const PathNode &b = M->path[(size_t)gr.path_off + k2];
+        if (k2 == k1 || !b.first) continue;
+        const int u = std::min(k1, k2), v = std::max(k1, k2);
+        const int q = u * (2 * d - u - 1) / 2 + (v - u - 1);
+        lists[(size_t)a.feat].push_back({b.feat, (int32_t)g, (int32_t)(M->iv_off[g] + ((int64_t)q << d))});
+      }
+    }
+  }
+  ioff.assign((size_t)F + 1, 0);
+  items.clear();
+  for (int f = 0; f < F; ++f) {
+    auto &l = lists[(size_t)f];
+    std::sort(l.begin(), l.end());
+    for (const auto &e : l) items.insert(items.end(), {e[2], (int32_t)((uint32_t)e[1] << 16 | (uint32_t)e[0])});
+    if (!l.empty())
+      while ((items.size() / 2) % 8) items.insert(items.end(), {(int32_t)M->iv_tab_size, l.back()[0]});
+    ioff[(size_t)f + 1] = (int32_t)(items.size() / 2);
+  }
+  if (items.empty()) items.assign(2, 0);
+  // Units of the interleaved tables (specialised kernel): per feature i,
+  // one per group where i has a first occurrence and a partner, in group
+  // order; a feature's units are contiguous in the tables.
+  std::vector<std::vector<IvUnit>> ufeat((size_t)F);
+  std::vector<std::vector<std::array<int32_t, 7>>> upart((size_t)F);
+  for (size_t g = 0; g < G; ++g) {
+    const Group &gr = M->groups[g];
+    const int d = gr.depth;
+    for (int k1 = 0; k1 < d; ++k1) {
+      const PathNode &a = M->path[(size_t)gr.path_off + k1];
+      if (!a.first) continue;
+      IvUnit u{};
+      std::array<int32_t, 7> js{};
+      u.src = M->iv_off[g];
+      u.depth = d;
+      u.group = (int32_t)g;
+      for (int k2 = 0; k2 < d; ++k2) {
+        const PathNode &b = M->path[(size_t)gr.path_off + k2];
+        if (k2 == k1 || !b.first) continue;
+        const int lo = std::min(k1, k2), hi = std::max(k1, k2);
+        js[(size_t)u.cnt] = b.feat;
+        u.q[u.cnt++] = lo * (2 * d - lo - 1) / 2 + (hi - lo - 1);
+      }
+      if (u.cnt > 0) {
+        ufeat[(size_t)a.feat].push_back(u);
+        upart[(size_t)a.feat].push_back(js);
+      }
+    }
+  }
+  M->iv_units.clear();
+  M->iv_unit_partners.clear();
+  M->iv_unit_off.assign((size_t)F + 1, 0);
+  int64_t dst = 0;
+  for (int f = 0; f < F; ++f) {
+    for (size_t k = 0; k < ufeat[(size_t)f].size(); ++k) {
+      IvUnit &u = ufeat[(size_t)f][k];
+      u.dst = dst;
+      dst += ivunit_floats(u);
+      M->iv_units.push_back(u);
+      M->iv_unit_partners.push_back(upart[(size_t)f][k]);
+    }
+    M->iv_unit_off[(size_t)f + 1] = (int32_t)M->iv_units.size();
+  }
+  M->iv_units_size = dst;
+  return WDF_OK;
+}
+
 static int prepare_iv(wdf_model *M, int kind) {
   hipStream_t s = M->ctx->stream;
   int rc;
   if (!M->iv_layout) {
-    const size_t G = M->groups.size();
-    M->iv_off.assign(G, 0);
-    int64_t off = 0;
-    for (size_t g = 0; g < G; ++g) {
-      const int d = M->groups[g].depth;
-      M->iv_off[g] = off;
-      off += ((((int64_t)d * (d - 1) / 2) << d) + 3) & ~(int64_t)3;
-    }
-    M->iv_tab_size = off;
-    int64_t so = 0;
-    for (int dp = 0; dp <= WDF_MAX_DEPTH; ++dp) {
-      M->s_iv_class_off[dp] = so;
-      so += (int64_t)M->cls[dp].ncols * (dp * (dp - 1) / 2) << dp;
-    }
-    M->s_iv_total = so;
-    // Work lists of the interaction kernel, one per feature i: for every
-    // group where i and another feature j both have a first occurrence on the
-    // path, one item (offset of the pair table of (i, j) in the interaction
-    // tables, group << 16 | j), sorted by j, then group.  Each list is padded
-    // to a multiple of 8 items with items of its last j that read the zero
-    // block after the tables.
-    const int F = M->n_features;
-    if (M->iv_tab_size + 256 >= ((int64_t)1 << 31))
-      return set_error(WDF_E_UNSUPPORTED, "interaction tables of %lld floats exceed 2^31", (long long)M->iv_tab_size);
-    if (G > 65535 || F > 65535)
-      return set_error(WDF_E_UNSUPPORTED, "interaction values: %zu groups or %d features exceed 65535", G, F);
-    std::vector<std::vector<std::array<int32_t, 3>>> lists((size_t)F);  // (j, group, table offset)
-    for (size_t g = 0; g < G; ++g) {
-      const Group &gr = M->groups[g];
-      const int d = gr.depth;
-      for (int k1 = 0; k1 < d; ++k1) {
-        const PathNode &a = M->path[(size_t)gr.path_off + k1];
-        if (!a.first) continue;
-        for (int k2 = 0; k2 < d; ++k2) {
-          const PathNode &b = M->path[(size_t)gr.path_off + k2];
-          if (k2 == k1 || !b.first) continue;
-          const int u = std::min(k1, k2), v = std::max(k1, k2);
-          const int q = u * (2 * d - u - 1) / 2 + (v - u - 1);
-          lists[(size_t)a.feat].push_back({b.feat, (int32_t)g, (int32_t)(M->iv_off[g] + ((int64_t)q << d))});
-        }
-      }
-    }
-    std::vector<int32_t> ioff((size_t)F + 1, 0), items;
-    for (int f = 0; f < F; ++f) {
-      auto &l = lists[(size_t)f];
-      std::sort(l.begin(), l.end());
-      for (const auto &e : l) items.insert(items.end(), {e[2], (int32_t)((uint32_t)e[1] << 16 | (uint32_t)e[0])});
-      if (!l.empty())
-        while ((items.size() / 2) % 8) items.insert(items.end(), {(int32_t)M->iv_tab_size, l.back()[0]});
-      ioff[(size_t)f + 1] = (int32_t)(items.size() / 2);
-    }
-    if (items.empty()) items.assign(2, 0);
+    std::vector<int32_t> ioff, items;
+    if ((rc = iv_layout_host(M, ioff, items))) return rc;
+    if ((rc = upload(M->d_iv_units, M->iv_units.empty() ? std::vector<IvUnit>(1) : M->iv_units, s))) return rc;
     std::vector<int64_t> soff(M->s_iv_class_off, M->s_iv_class_off + WDF_MAX_DEPTH + 1);
     if ((rc = upload(M->d_iv_off, M->iv_off.empty() ? std::vector<int64_t>(1, 0) : M->iv_off, s))) return rc;
     if ((rc = upload(M->d_siv_class_off, soff, s))) return rc;
@@ -576,6 +635,10 @@ static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
     if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->jp.xtab_size, 1) * sizeof(float)))) return rc;
     HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
   }
+  if (bg->iv_spec) {
+    if ((rc = bg->d_xtab.alloc((size_t)std::max<int64_t>(M->iv_units_size, 1) * sizeof(float)))) return rc;
+    HIP_TRY(hipMemsetAsync(bg->d_xtab.ptr, 0, bg->d_xtab.bytes, s));
+  }
   return WDF_OK;
 }
 
@@ -597,6 +660,9 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
     }
     HIP_TRY(launch_expand_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_off.as<int64_t>(),
                              M->d_siv_class_off.as<int64_t>(), S, bg->d_tab.as<float>(), s));
+    if (bg->iv_spec)  // interleaved tables of the specialised interaction kernel
+      HIP_TRY(launch_ivtab(M->d_iv_units.as<IvUnit>(), (int64_t)M->iv_units.size(), bg->d_tab.as<float>(),
+                           bg->d_xtab.as<float>(), s));
     HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
     return WDF_OK;
   }
@@ -654,6 +720,11 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   if (bg->iv) {
     int rc_iv;
     if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
+    if (M->jit) {  // the specialised interaction kernel, unless the model is too large for it
+      rc_iv = jit_build_iv(M);
+      if (rc_iv != WDF_OK && rc_iv != WDF_E_UNSUPPORTED) return rc_iv;
+      bg->iv_spec = rc_iv == WDF_OK;
+    }
   }
   int rc;
   DevBuf Bcopy;
@@ -806,6 +877,11 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   if (bg->iv) {
     int rc_iv;
     if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
+    if (M->jit) {  // the specialised interaction kernel, unless the model is too large for it
+      rc_iv = jit_build_iv(M);
+      if (rc_iv != WDF_OK && rc_iv != WDF_E_UNSUPPORTED) return rc_iv;
+      bg->iv_spec = rc_iv == WDF_OK;
+    }
   }
   bg->pathdep = true;
   int rc;
@@ -874,6 +950,11 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
     return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
                      (long long)(G * n));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
+  if (bg->iv_spec) {
+    HIP_TRY(launch_patterns_u8(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, X, n, ldx, (uint8_t *)workspace,
+                               s));
+    return jit_explain_iv(bg, (const uint8_t *)workspace, n, iv, ldiv, s);
+  }
   HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_item_off.as<int32_t>(),
                             M->d_iv_items.as<int2>(), bg->d_tab.as<float>(), X, n, ldx, (uint8_t *)workspace, iv, ldiv,
                             M->n_features, s));
@@ -938,6 +1019,22 @@ extern "C" int64_t wdf_debug_coef_matrix(int dprime, int values, double *out, in
   }
   if (out && cap >= (int64_t)M.size()) std::memcpy(out, M.data(), M.size() * sizeof(double));
   return (int64_t)M.size();
+}
+
+extern "C" int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, int64_t cap) {
+  if (!desc) return set_error(WDF_E_INVALID_ARG, "wdf_debug_iv_source: NULL desc");
+  try {
+    wdf_model M;
+    int rc = validate_and_layout(desc, &M);
+    if (rc) return rc;
+    std::vector<int32_t> ioff, items;
+    if ((rc = iv_layout_host(&M, ioff, items))) return rc;
+    const std::string src = jit_iv_source(&M);
+    if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);
+    return (int64_t)src.size();
+  } catch (const std::bad_alloc &) {
+    return set_error(WDF_E_OOM, "wdf_debug_iv_source: out of host memory");
+  }
 }
 
 extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int do_compile, char *out,

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 
 #include <map>
@@ -139,6 +140,13 @@ struct wdf_model {
   int64_t iv_tab_size = 0, s_iv_total = 0;
   int64_t s_iv_class_off[WDF_MAX_DEPTH + 1] = {};
   wdf::DevBuf d_iv_off, d_siv_class_off, d_iv_item_off, d_iv_items;
+  // interleaved interaction tables of the specialised interaction kernel:
+  // units grouped by feature (iv_unit_off[i] .. iv_unit_off[i + 1])
+  std::vector<wdf::IvUnit> iv_units;
+  std::vector<std::array<int32_t, 7>> iv_unit_partners;  // partner features of each unit
+  std::vector<int32_t> iv_unit_off;
+  int64_t iv_units_size = 0;   // floats
+  wdf::DevBuf d_iv_units;
   bool iv_coef_ready[2] = {false, false};
   wdf::DevBuf d_coef_iv[2][WDF_MAX_DEPTH + 1];  // [Shapley/Banzhaf][dprime]
 };
@@ -153,7 +161,9 @@ struct wdf_bg {
   double base = 0.0;
   wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)
   wdf::DevBuf d_tab;    // float gather tables
-  wdf::DevBuf d_xtab;   // explain tables of the specialised kernel (quads merged)
+  wdf::DevBuf d_xtab;   // explain tables of the specialised kernel (quads merged), or the
+                        // interleaved interaction tables (iv_spec)
+  bool iv_spec = false; // interaction summary explained by the specialised kernel
   // private workspace of in-place refreshes (allocated by the first one):
   // threshold ranks, contraction columns and products, the base value
   wdf::DevBuf own_codes, own_H, own_S, d_base;
@@ -171,6 +181,11 @@ struct wdf_graph {
 namespace wdf {
 // Model-specialised kernels (wdf_jit.cpp).
 int jit_build(wdf_model *M);
+// the specialised interaction kernel (compiled on first use; WDF_E_UNSUPPORTED
+// when the model is too large for it)
+int jit_build_iv(wdf_model *M);
+std::string jit_iv_source(const wdf_model *M);
+int jit_explain_iv(const wdf_bg *bg, const uint8_t *pat, int64_t n, float *iv, int64_t ldiv, hipStream_t s);
 int jit_source(wdf_model *M, bool do_compile, std::string &src);
 int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
 // background histograms; `codes` holds P.words * m words of threshold ranks

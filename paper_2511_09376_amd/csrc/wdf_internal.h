@@ -26,6 +26,10 @@ hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const 
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s);
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,
                             const int64_t *s_class_off, const double *S, float *tab, hipStream_t s);
+hipError_t launch_ivtab(const IvUnit *units, int64_t n_units, const float *tab, float *t2, hipStream_t s);
+// patterns of every group into pat (n_groups * n bytes)
+hipError_t launch_patterns_u8(const Group *groups, const PathNode *path, int64_t n_groups, const float *X, int64_t n,
+                              int64_t ldx, uint8_t *pat, hipStream_t s);
 // patterns of every group into pat (n_groups * n bytes), then the interaction kernel
 hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int32_t *item_off,
                              const int2 *items, const float *tab, const float *X, int64_t n, int64_t ldx, uint8_t *pat,

@@ -40,8 +40,9 @@ struct JitPart {
 };
 
 struct JitModule {
-  std::shared_ptr<JitPart> hist_part, explain_part;
+  std::shared_ptr<JitPart> hist_part, explain_part, iv_part;
   hipFunction_t hist = nullptr, explain = nullptr;
+  std::vector<hipFunction_t> iv;  // interaction kernels, features [c * 4, c * 4 + 4)
 };
 
 namespace {
@@ -875,6 +876,130 @@ int jit_build(wdf_model *M) {
     return hip_error(e, "hipMemcpyAsync(perm)");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   M->jit = mod;
+  return WDF_OK;
+}
+
+// Interaction values, specialised: one wave = 64 rows and one feature i (a
+// case of the switch on blockIdx.y).  For every unit of i (a group where i
+// has a first occurrence), the rows' pattern of the group is read from the
+// workspace and each 16-byte read of the interleaved tables returns the pair
+// values of four partners, added into registers with static indices (one per
+// partner feature of i).  Then the row's iv[i][j] for every j, zeros where i
+// has no pair with j (the diagonal among them).
+namespace {
+
+int64_t iv_spec_ops(const wdf_model *M) {
+  int64_t ops = 0;
+  for (const IvUnit &u : M->iv_units) ops += 1 + (u.cnt + 3) / 4 + u.cnt;
+  return ops;
+}
+
+constexpr int kIvBatch = 4;     // units per basic block of the interaction kernels
+constexpr int kIvPerKernel = 4; // features per interaction kernel (compile time grows
+                                // faster than linearly with a function's size)
+
+std::string iv_kernel_name(int c) { return "wdf_iv_spec_" + std::to_string(c); }
+
+std::string gen_iv(const wdf_model *M) {
+  const int F = M->n_features;
+  std::ostringstream o;
+  o << kPreamble << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
+  static const char *C[4] = {"x", "y", "z", "w"};
+  for (int c = 0; c * kIvPerKernel < F; ++c) {
+    o << "extern \"C\" __global__ __launch_bounds__(256) void " << iv_kernel_name(c)
+      << "(const unsigned char* __restrict__ pat, i64 n, const float* __restrict__ t2, float* __restrict__ out, "
+         "i64 ldo, int live) {\n"
+      << "  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;\n"
+      << "  const i64 row = ((i64)blockIdx.x * 4 + wave) * 64 + lane;\n"
+      << "  const i64 rr = row < n ? row : n - 1;\n"
+      << "  float* o = out + row;\n"
+      << "  switch (blockIdx.y) {\n";
+    for (int i = c * kIvPerKernel; i < std::min(F, (c + 1) * kIvPerKernel); ++i) {
+      const int u0 = M->iv_unit_off[(size_t)i], u1 = M->iv_unit_off[(size_t)i + 1];
+      std::vector<char> partner((size_t)F, 0);
+      for (int k = u0; k < u1; ++k)
+        for (int s = 0; s < M->iv_units[(size_t)k].cnt; ++s)
+          partner[(size_t)M->iv_unit_partners[(size_t)k][(size_t)s]] = 1;
+      o << "  case " << i - c * kIvPerKernel << ": {\n";
+      for (int j = 0; j < F; ++j)
+        if (partner[(size_t)j]) o << "    float a" << j << " = 0.f;\n";
+      // `live` is always 1: the branches split the code into basic blocks of
+      // kIvBatch units, so that the scheduler does not hoist all of a case's
+      // loads to its top (registers)
+      for (int k = u0; k < u1; ++k) {
+        const IvUnit &u = M->iv_units[(size_t)k];
+        const int64_t E = (int64_t)1 << u.depth;
+        if ((k - u0) % kIvBatch == 0) o << "    if (live) {\n";
+        o << "    { const u32 p = pat[(i64)" << u.group << " * n + rr]; const vf4* t = (const vf4*)(t2 + " << u.dst
+          << ") + p;";
+        for (int pl = 0; 4 * pl < u.cnt; ++pl) {
+          o << " { const vf4 v = t[" << pl * E << "];";
+          for (int cc = 0; cc < 4 && 4 * pl + cc < u.cnt; ++cc)
+            o << " a" << M->iv_unit_partners[(size_t)k][(size_t)(4 * pl + cc)] << " += v." << C[cc] << ";";
+          o << " }";
+        }
+        o << " }\n";
+        if ((k - u0) % kIvBatch == kIvBatch - 1 || k + 1 == u1) o << "    }\n";
+      }
+      o << "    if (row < n) {\n";
+      for (int j = 0; j < F; ++j)
+        o << "      o[(i64)" << (int64_t)i * F + j << " * ldo] = "
+          << (partner[(size_t)j] ? "a" + std::to_string(j) : std::string("0.f")) << ";\n";
+      o << "    }\n  } break;\n";
+    }
+    o << "  default: break;\n  }\n}\n";
+  }
+  return o.str();
+}
+
+// Largest interaction model for the specialised kernel (loads and adds of all
+// its units); larger ones use the generic kernel.
+const int64_t kMaxIvSpecOps = 400000;
+
+}  // namespace
+
+std::string jit_iv_source(const wdf_model *M) { return gen_iv(M); }
+
+int jit_build_iv(wdf_model *M) {
+  if (!M->jit) return set_error(WDF_E_UNSUPPORTED, "specialised interaction kernel: the model runs the generic kernels");
+  if (!M->jit->iv.empty()) return WDF_OK;
+  if (M->iv_units.empty() || iv_spec_ops(M) > kMaxIvSpecOps)
+    return set_error(WDF_E_UNSUPPORTED, "specialised interaction kernel: %lld table loads and adds exceed %lld",
+                     (long long)iv_spec_ops(M), (long long)kMaxIvSpecOps);
+  const std::string src = gen_iv(M);
+  std::shared_ptr<JitPart> part = cached_part(M, src);
+  if (!part) {
+    std::vector<char> code;
+    int rc = compile(src, code);
+    if (rc) return rc;
+    if ((rc = load_part(M, src, code, iv_kernel_name(0).c_str(), part))) return rc;
+  }
+  std::vector<hipFunction_t> fns;
+  for (int c = 0; c * kIvPerKernel < M->n_features; ++c) {
+    hipFunction_t f = nullptr;
+    hipError_t e = hipModuleGetFunction(&f, part->mod, iv_kernel_name(c).c_str());
+    if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(interaction)");
+    fns.push_back(f);
+  }
+  M->jit->iv_part = part;
+  M->jit->iv = fns;
+  return WDF_OK;
+}
+
+int jit_explain_iv(const wdf_bg *bg, const uint8_t *pat, int64_t n, float *iv, int64_t ldiv, hipStream_t s) {
+  const wdf_model *M = bg->model;
+  if (!M->jit || M->jit->iv.empty()) return set_error(WDF_E_INVALID_ARG, "specialised interaction kernel missing");
+  if (n <= 0) return WDF_OK;
+  const float *t2 = bg->d_xtab.as<float>();
+  int live = 1;
+  void *args[] = {(void *)&pat, &n, (void *)&t2, &iv, &ldiv, &live};
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  const int F = M->n_features;
+  for (int c = 0; c < (int)M->jit->iv.size(); ++c) {
+    const unsigned fc = (unsigned)std::min(kIvPerKernel, F - c * kIvPerKernel);
+    hipError_t e = hipModuleLaunchKernel(M->jit->iv[(size_t)c], blocks, fc, 1, 256, 1, 1, 0, s, args, nullptr);
+    if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(interaction)");
+  }
   return WDF_OK;
 }
 

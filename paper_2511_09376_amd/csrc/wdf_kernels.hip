@@ -422,6 +422,26 @@ __global__ __launch_bounds__(256) void k_expand_iv(const Group *__restrict__ gro
   }
 }
 
+// Interleaved interaction tables (IvUnit): entry [plane][p][c] of a unit is
+// the pair table of (i, partner 4 plane + c) at pattern p, 0 past the last
+// partner.
+__global__ __launch_bounds__(256) void k_ivtab(const IvUnit *__restrict__ units, const float *__restrict__ tab,
+                                               float *__restrict__ t2) {
+  const IvUnit u = units[blockIdx.x];
+  const int d = u.depth, E = 1 << d;
+  const int total = 4 * ((u.cnt + 3) / 4) * E;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int c = idx & 3, p = (idx >> 2) & (E - 1), s = (idx >> (d + 2)) * 4 + c;
+    t2[u.dst + idx] = s < u.cnt ? tab[u.src + ((int64_t)u.q[s] << d) + p] : 0.f;
+  }
+}
+
+hipError_t launch_ivtab(const IvUnit *units, int64_t n_units, const float *tab, float *t2, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ivtab, dim3((unsigned)n_units), dim3(256), 0, s, units, tab, t2);
+  return hipGetLastError();
+}
+
 // Patterns of every group for every row, one byte each (depth <= 8):
 // pat[g * n + r].  Computed once per call, read by every feature's wave.
 __global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ groups,
@@ -432,6 +452,15 @@ __global__ __launch_bounds__(256) void k_patterns_u8(const Group *__restrict__ g
   const int64_t gi = blockIdx.y;
   pat[gi * n + r] = (uint8_t)group_pattern(groups[gi], path, X, ldx, r);
 }
+
+hipError_t launch_patterns_u8(const Group *groups, const PathNode *path, int64_t n_groups, const float *X, int64_t n,
+                              int64_t ldx, uint8_t *pat, hipStream_t s) {
+  if (n <= 0 || n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_patterns_u8, dim3((unsigned)((n + 255) / 256), (unsigned)n_groups), dim3(256), 0, s, groups,
+                     path, X, n, ldx, pat);
+  return hipGetLastError();
+}
+
 
 // Interaction values of consumer rows: one wave = 64 rows and one feature i
 // (blockIdx.y).  The wave walks the work list of i: items (offset of the pair

@@ -99,10 +99,10 @@ class Tuning(C.Structure):
 
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
-    "wdf_model_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
+    "wdf_model_specialised", "wdf_bg_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
     "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
-    "wdf_debug_specialised_source", "wdf_debug_coef_matrix", "wdf_model_autotune", "wdf_server_create",
+    "wdf_debug_specialised_source", "wdf_debug_iv_source", "wdf_debug_coef_matrix", "wdf_model_autotune", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
 
@@ -123,6 +123,7 @@ def lib():
         L.wdf_model_groups.argtypes = [P, P, P, P, P, P, P]
         L.wdf_model_groups.restype = I64
         L.wdf_model_specialised.argtypes = [P]
+        L.wdf_bg_specialised.argtypes = [P]
         L.wdf_background_load.argtypes = [P, P, I64, I64, I, I, P, C.POINTER(P)]
         L.wdf_pathdep_load.argtypes = [P, I, P, C.POINTER(P)]
         L.wdf_bg_destroy.argtypes = [P]
@@ -142,6 +143,8 @@ def lib():
         L.wdf_debug_tables.restype = I64
         L.wdf_debug_specialised_source.argtypes = [P, I, I, P, I64]
         L.wdf_debug_specialised_source.restype = I64
+        L.wdf_debug_iv_source.argtypes = [P, P, I64]
+        L.wdf_debug_iv_source.restype = I64
         L.wdf_debug_coef_matrix.argtypes = [I, I, P, I64]
         L.wdf_debug_coef_matrix.restype = I64
         L.wdf_model_autotune.argtypes = [P, P, I64, I64, P, I64, I64, P, C.POINTER(Tuning)]
@@ -198,6 +201,15 @@ def specialised_source(ens, compile: bool = False, kernel: int = KERNEL_SPECIALI
     n = _check(lib().wdf_debug_specialised_source(C.byref(desc), kernel, int(compile), None, 0))
     buf = C.create_string_buffer(n + 1)
     _check(lib().wdf_debug_specialised_source(C.byref(desc), kernel, 0, buf, n + 1))
+    return buf.value.decode()
+
+
+def iv_source(ens) -> str:
+    """Generated source of the specialised interaction-value kernel (no GPU needed)."""
+    desc, keep = _model_desc(ens)
+    n = _check(lib().wdf_debug_iv_source(C.byref(desc), None, 0))
+    buf = C.create_string_buffer(n + 1)
+    _check(lib().wdf_debug_iv_source(C.byref(desc), buf, n + 1))
     return buf.value.decode()
 
 
@@ -324,6 +336,11 @@ class Background:
             self.m = m
         self.h = h
         _track(self)
+
+    @property
+    def specialised(self) -> bool:
+        """Explained by model-specialised kernels (else the generic ones)."""
+        return bool(lib().wdf_bg_specialised(self.h))
 
     @property
     def base_value(self) -> float:

@@ -90,6 +90,45 @@ def test_mid_iv_sampled_rows(wdf, ctx):
     assert np.isfinite(got).all()
 
 
+def _groups_per_feature(ens):
+    """Leaf groups (pairs and singles) whose path carries each feature."""
+    K = np.zeros(ens.n_features, np.int64)
+    for t in range(ens.n_trees):
+        sl = ens.tree_slice(t)
+        f, l, r = ens.feature[sl], ens.left[sl], ens.right[sl]
+        parent = {}
+        for i in range(len(f)):
+            if f[i] >= 0:
+                parent[int(l[i])] = i
+                parent[int(r[i])] = i
+        for i in range(len(f)):
+            if f[i] >= 0 and (f[l[i]] < 0 or f[r[i]] < 0):
+                feats, x = set(), i
+                while True:
+                    feats.add(int(f[x]))
+                    if x not in parent:
+                        break
+                    x = parent[x]
+                for a in feats:
+                    K[a] += 1
+    return K
+
+
+def test_iv_many_groups_per_feature(wdf, ctx):
+    """200 depth-4 trees over 3 of 8 features: each feature lies on more than
+    a thousand group paths (long work lists, runs of many items per partner)."""
+    ens = synth.make_ensemble(synth.ModelSpec(200, 4, 4, 0.0, 8, feature_pool=3), synth.DataSpec(8, False, 0.0), 11)
+    assert _groups_per_feature(ens).max() > 512
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(8, 70)).astype(np.float32)
+    B = rng.normal(size=(8, 41)).astype(np.float32)
+    model = wdf.Model(ctx, ens, wdf.KERNEL_AUTO)
+    bg = wdf.Background(model, _cuda(B), values=wdf.SHAPLEY_IV)
+    got = bg.explain_iv(_cuda(X)).cpu().numpy()
+    ref = oracle.bg_iv_walk(oracle.Model(ens), X, B, threads=8)
+    assert _iv_error(got, ref) <= 1e-5
+
+
 def test_iv_refresh_and_refusals(wdf, ctx):
     w = synth.WORKLOADS["small"]
     ens, X = w.ensemble(), w.consumers()

@@ -59,6 +59,60 @@ def test_gather_counts_match_the_layout(wdf):
         assert f"phi[{f} * ldphi + row]" in pairs
 
 
+def _path_feature_sets(ens):
+    """Distinct features on the path of every leaf group (a pair of sibling
+    leaves, or a leaf whose sibling is an inner node)."""
+    out = []
+    for t in range(ens.n_trees):
+        sl = ens.tree_slice(t)
+        f, l, r = ens.feature[sl], ens.left[sl], ens.right[sl]
+        parent = {}
+        for i in range(len(f)):
+            if f[i] >= 0:
+                parent[int(l[i])] = i
+                parent[int(r[i])] = i
+        for i in range(len(f)):
+            if f[i] < 0:
+                continue
+            for leaf_side in (int(l[i]), int(r[i])):
+                if f[leaf_side] >= 0:
+                    continue
+                if leaf_side == int(r[i]) and f[l[i]] < 0:
+                    continue  # the pair was counted with its left leaf
+                feats, x = set(), i
+                while True:
+                    feats.add(int(f[x]))
+                    if x not in parent:
+                        break
+                    x = parent[x]
+                out.append(feats)
+    return out
+
+
+@pytest.mark.parametrize("which", ["small", "edge"])
+def test_iv_source_matches_the_layout(wdf, which):
+    """The specialised interaction kernels add one pair value per (group,
+    feature i at its first occurrence, partner j), i.e. sum over groups of
+    d'(d' - 1) adds; one kernel per four features; every output iv[i][j] is
+    written once per row, the diagonal as 0."""
+    ens = synth.WORKLOADS["small"].ensemble() if which == "small" else _edge()
+    F = ens.n_features
+    src = wdf.iv_source(ens)
+    sets = _path_feature_sets(ens)
+    assert len(re.findall(r"\+= v\.", src)) == sum(len(s) * (len(s) - 1) for s in sets)
+    assert src.count('extern "C"') == (F + 3) // 4
+    writes = re.findall(r"o\[\(i64\)(\d+) \* ldo\] = (\S+);", src)
+    assert sorted(int(k) for k, _ in writes) == list(range(F * F))
+    for k, v in writes:
+        i, j = divmod(int(k), F)
+        if i == j:
+            assert v == "0.f"
+        elif not any(i in s and j in s for s in sets):
+            assert v == "0.f"
+        else:
+            assert v == f"a{j}"
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("values", ["shapley", "banzhaf", "shapley_iv", "banzhaf_iv"])
 def test_host_coefficient_matrices_match_the_oracle(wdf, d, values):
