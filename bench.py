@@ -306,7 +306,7 @@ def main():
         achieved = out_bytes / (explain_ms * 1e-3)
         roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK, "traffic": None,
-                    "kernel": ("k_patterns_u8 + wdf_iv_spec_*" if bg.specialised else "k_patterns_u8 + k_explain_iv"),
+                    "kernel": ("wdf_patterns_spec + wdf_iv_spec_*" if bg.specialised else "k_patterns_u8 + k_explain_iv"),
                     "kernel_ms": explain_ms, "bytes_per_row": 4 * ens.n_features ** 2}
     else:
         ops_row = int(method_ops_per_row(ens))

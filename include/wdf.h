@@ -243,11 +243,12 @@ int64_t wdf_debug_coef_matrix(int dprime, int values, double *out, int64_t cap);
  * WDF_KERNEL_PAIRS matters here).  For tools and tests; needs no GPU. */
 int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int compile, char *out, int64_t cap);
 
-/* Generated source of the model's specialised interaction-value kernel
- * (wdf_explain_iv on a summary of a model with specialised kernels; it adds
- * the pair tables of Table table_shap_iv / Formula
- * banzhaf_simplified_formula_interactions, laid out per (group, feature) and
- * interleaved by pattern).  Same buffer convention as
+/* Generated source of the model's specialised interaction-value kernels
+ * (wdf_explain_iv on a summary of a model with specialised kernels): the
+ * consumer patterns of every group (Def. Decision Pattern) into the
+ * workspace, and the kernels that add the pair tables of Table table_shap_iv /
+ * Formula banzhaf_simplified_formula_interactions, laid out per (group,
+ * feature) and interleaved by pattern.  Same buffer convention as
  * wdf_debug_specialised_source; needs no GPU. */
 int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, int64_t cap);
 

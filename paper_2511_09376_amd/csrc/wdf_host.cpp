@@ -950,11 +950,7 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
     return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
                      (long long)(G * n));
   hipStream_t s = pick_stream(M->ctx, hip_stream);
-  if (bg->iv_spec) {
-    HIP_TRY(launch_patterns_u8(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, X, n, ldx, (uint8_t *)workspace,
-                               s));
-    return jit_explain_iv(bg, (const uint8_t *)workspace, n, iv, ldiv, s);
-  }
+  if (bg->iv_spec) return jit_explain_iv(bg, X, ldx, (uint8_t *)workspace, n, iv, ldiv, s);
   HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_item_off.as<int32_t>(),
                             M->d_iv_items.as<int2>(), bg->d_tab.as<float>(), X, n, ldx, (uint8_t *)workspace, iv, ldiv,
                             M->n_features, s));
@@ -1029,7 +1025,8 @@ extern "C" int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, in
     if (rc) return rc;
     std::vector<int32_t> ioff, items;
     if ((rc = iv_layout_host(&M, ioff, items))) return rc;
-    const std::string src = jit_iv_source(&M);
+    std::string src;
+    if ((rc = jit_iv_source(&M, src))) return rc;
     if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);
     return (int64_t)src.size();
   } catch (const std::bad_alloc &) {

@@ -184,8 +184,10 @@ int jit_build(wdf_model *M);
 // the specialised interaction kernel (compiled on first use; WDF_E_UNSUPPORTED
 // when the model is too large for it)
 int jit_build_iv(wdf_model *M);
-std::string jit_iv_source(const wdf_model *M);
-int jit_explain_iv(const wdf_bg *bg, const uint8_t *pat, int64_t n, float *iv, int64_t ldiv, hipStream_t s);
+int jit_iv_source(wdf_model *M, std::string &src);  // interaction and pattern kernels (plans the model)
+// patterns of the consumer rows into the workspace pat, then the interaction kernels
+int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, int64_t n, float *iv, int64_t ldiv,
+                   hipStream_t s);
 int jit_source(wdf_model *M, bool do_compile, std::string &src);
 int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
 // background histograms; `codes` holds P.words * m words of threshold ranks

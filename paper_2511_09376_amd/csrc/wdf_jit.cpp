@@ -43,6 +43,7 @@ struct JitModule {
   std::shared_ptr<JitPart> hist_part, explain_part, iv_part;
   hipFunction_t hist = nullptr, explain = nullptr;
   std::vector<hipFunction_t> iv;  // interaction kernels, features [c * 4, c * 4 + 4)
+  hipFunction_t patterns = nullptr;  // all groups' patterns of consumer rows, for the interaction kernels
 };
 
 namespace {
@@ -574,6 +575,55 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
   return o.str();
 }
 
+// Threshold ranks of the row (X[f * ldx + rr]) packed into the words w*, as
+// the pattern code expects; thresholds from lthr (LDS) or thr.  The searches
+// run step-major over batches of 16 features so that 16 independent reads
+// are in flight at every step.
+void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char> &used, bool lds_thr) {
+  const JitPlan &P = M->jp;
+  const int F = M->n_features;
+  for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
+
+  // threshold ranks of the row, packed as the pattern kernels expect.  The
+  // searches run step-major over batches of 16 features so that 16
+  // independent LDS reads are in flight at every step.
+  const int bits = P.wide ? 16 : 8;
+  std::vector<int> uf;
+  for (int f = 0; f < F; ++f)
+    if (used[(size_t)f]) uf.push_back(f);
+  std::vector<char> word_open((size_t)P.words, 0);
+  for (size_t b0 = 0; b0 < uf.size(); b0 += 16) {
+    const size_t b1 = std::min(uf.size(), b0 + 16);
+    o << "  if (live) {\n";  // one basic block per batch: its loads are not hoisted into the previous one
+    int cmax = 0;
+    for (size_t i = b0; i < b1; ++i) {
+      const int f = uf[i];
+      o << "  const float x" << f << " = X[(i64)" << f << " * ldx + rr]; u32 r" << f << " = 0u;\n";
+      cmax = std::max(cmax, P.thr_steps[(size_t)f]);
+    }
+    for (int k = cmax - 1; k >= 0; --k) {
+      o << " ";
+      for (size_t i = b0; i < b1; ++i) {
+        const int f = uf[i];
+        if (P.thr_steps[(size_t)f] <= k) continue;
+        o << " r" << f << " += (" << (lds_thr ? "lthr[" : "thr[") << P.thr_pad_off[(size_t)f] + (1 << k) - 1 << " + r" << f << "] <= x" << f
+          << ") ? " << (1u << k) << "u : 0u;";
+      }
+      o << "\n";
+    }
+    for (size_t i = b0; i < b1; ++i) {
+      const int f = uf[i], w = f / P.per_word, sft = (f % P.per_word) * bits;
+      if (!word_open[(size_t)w]) {
+        word_open[(size_t)w] = 1;
+        o << "  w" << w << " = 0u;\n";
+      }
+      o << "  w" << w << " |= (x" << f << " != x" << f << " ? " << (1u << (bits - 1)) << "u : r" << f << ") << " << sft
+        << ";\n";
+    }
+    o << "  }\n";
+  }
+}
+
 std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   const JitPlan &P = M->jp;
   const int F = M->n_features;
@@ -624,46 +674,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   if (P.thr_in_lds)
     o << "  float* lthr = lds + " << (thr_hi ? P.stage_floats : 0) << ";\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
-  for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
-
-  // threshold ranks of the row, packed as the pattern kernels expect.  The
-  // searches run step-major over batches of 16 features so that 16
-  // independent LDS reads are in flight at every step.
-  const int bits = P.wide ? 16 : 8;
-  std::vector<int> uf;
-  for (int f = 0; f < F; ++f)
-    if (used[(size_t)f]) uf.push_back(f);
-  std::vector<char> word_open((size_t)P.words, 0);
-  for (size_t b0 = 0; b0 < uf.size(); b0 += 16) {
-    const size_t b1 = std::min(uf.size(), b0 + 16);
-    o << "  if (live) {\n";  // one basic block per batch: its loads are not hoisted into the previous one
-    int cmax = 0;
-    for (size_t i = b0; i < b1; ++i) {
-      const int f = uf[i];
-      o << "  const float x" << f << " = X[(i64)" << f << " * ldx + rr]; u32 r" << f << " = 0u;\n";
-      cmax = std::max(cmax, P.thr_steps[(size_t)f]);
-    }
-    for (int k = cmax - 1; k >= 0; --k) {
-      o << " ";
-      for (size_t i = b0; i < b1; ++i) {
-        const int f = uf[i];
-        if (P.thr_steps[(size_t)f] <= k) continue;
-        o << " r" << f << " += (" << (P.thr_in_lds ? "lthr[" : "thr[") << P.thr_pad_off[(size_t)f] + (1 << k) - 1 << " + r" << f << "] <= x" << f
-          << ") ? " << (1u << k) << "u : 0u;";
-      }
-      o << "\n";
-    }
-    for (size_t i = b0; i < b1; ++i) {
-      const int f = uf[i], w = f / P.per_word, sft = (f % P.per_word) * bits;
-      if (!word_open[(size_t)w]) {
-        word_open[(size_t)w] = 1;
-        o << "  w" << w << " = 0u;\n";
-      }
-      o << "  w" << w << " |= (x" << f << " != x" << f << " ? " << (1u << (bits - 1)) << "u : r" << f << ") << " << sft
-        << ";\n";
-    }
-    o << "  }\n";
-  }
+  emit_rank_words(o, M, used, P.thr_in_lds);
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
@@ -952,13 +963,55 @@ std::string gen_iv(const wdf_model *M) {
   return o.str();
 }
 
+// Patterns of every group for every row (Def. Decision Pattern: bit 1 = the
+// row follows the group's path, root bit first), one byte per (group, row)
+// into pat[g * n + row]: one thread per row, the row's threshold ranks in
+// registers, the node tests of all trees in straight-line code (raw splits,
+// turned into path bits by the group's right turns), one store per group.
+constexpr int64_t kPatLdsThresholds = 16384;  // thresholds staged in LDS up to 64 KB
+
+std::string gen_patterns(const wdf_model *M, const TreeIndex &ix) {
+  const JitPlan &P = M->jp;
+  const int F = M->n_features;
+  const bool lds = (int64_t)P.thr_pad.size() <= kPatLdsThresholds;
+  Gen gen{M, ix};
+  std::ostringstream &o = gen.o;
+  std::vector<char> used((size_t)F, 0);
+  for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
+  o << "extern \"C\" __global__ __launch_bounds__(256) void wdf_patterns_spec(const float* __restrict__ X, i64 ldx, "
+       "const float* __restrict__ thr, unsigned char* __restrict__ pat, i64 n, int live) {\n"
+    << "  const u32 zero = 0u;\n"
+    << "  const i64 row = (i64)blockIdx.x * 256 + threadIdx.x;\n"
+    << "  const i64 rr = row < n ? row : n - 1;\n";
+  if (lds)
+    o << "  extern __shared__ float lthr[];\n"
+      << "  for (int i = threadIdx.x; i < " << P.thr_pad.size() << "; i += 256) lthr[i] = thr[i];\n"
+      << "  __syncthreads();\n";
+  emit_rank_words(o, M, used, lds);
+  gen.on_group = [&](int64_t g, const std::string &p) {
+    const Group &gr = M->groups[(size_t)g];
+    uint32_t mask = 0;
+    for (int k = 0; k < gr.depth; ++k)
+      if (M->path[(size_t)gr.path_off + k].dir) mask |= 1u << (gr.depth - 1 - k);
+    o << "if (row < n) pat[(i64)" << g << " * n + row] = (unsigned char)(" << p << " ^ " << mask << "u);\n";
+  };
+  if (!M->groups.empty()) gen.range(0, (int64_t)M->groups.size());
+  o << "}\n";
+  return o.str();
+}
+
 // Largest interaction model for the specialised kernel (loads and adds of all
 // its units); larger ones use the generic kernel.
 const int64_t kMaxIvSpecOps = 400000;
 
 }  // namespace
 
-std::string jit_iv_source(const wdf_model *M) { return gen_iv(M); }
+int jit_iv_source(wdf_model *M, std::string &src) {
+  const int rc = make_plan(M);
+  if (rc) return rc;
+  src = gen_iv(M) + gen_patterns(M, index_tree_groups(M));
+  return WDF_OK;
+}
 
 int jit_build_iv(wdf_model *M) {
   if (!M->jit) return set_error(WDF_E_UNSUPPORTED, "specialised interaction kernel: the model runs the generic kernels");
@@ -966,7 +1019,7 @@ int jit_build_iv(wdf_model *M) {
   if (M->iv_units.empty() || iv_spec_ops(M) > kMaxIvSpecOps)
     return set_error(WDF_E_UNSUPPORTED, "specialised interaction kernel: %lld table loads and adds exceed %lld",
                      (long long)iv_spec_ops(M), (long long)kMaxIvSpecOps);
-  const std::string src = gen_iv(M);
+  const std::string src = gen_iv(M) + gen_patterns(M, index_tree_groups(M));
   std::shared_ptr<JitPart> part = cached_part(M, src);
   if (!part) {
     std::vector<char> code;
@@ -981,15 +1034,31 @@ int jit_build_iv(wdf_model *M) {
     if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(interaction)");
     fns.push_back(f);
   }
+  hipFunction_t pf = nullptr;
+  hipError_t e = hipModuleGetFunction(&pf, part->mod, "wdf_patterns_spec");
+  if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(patterns)");
   M->jit->iv_part = part;
   M->jit->iv = fns;
+  M->jit->patterns = pf;
   return WDF_OK;
 }
 
-int jit_explain_iv(const wdf_bg *bg, const uint8_t *pat, int64_t n, float *iv, int64_t ldiv, hipStream_t s) {
+int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, int64_t n, float *iv, int64_t ldiv,
+                   hipStream_t s) {
   const wdf_model *M = bg->model;
-  if (!M->jit || M->jit->iv.empty()) return set_error(WDF_E_INVALID_ARG, "specialised interaction kernel missing");
+  if (!M->jit || M->jit->iv.empty() || !M->jit->patterns)
+    return set_error(WDF_E_INVALID_ARG, "specialised interaction kernel missing");
   if (n <= 0) return WDF_OK;
+  {
+    const JitPlan &P = M->jp;
+    const float *thr = P.d_thr_pad.as<float>();
+    int live = 1;
+    void *pargs[] = {(void *)&X, &ldx, (void *)&thr, &pat, &n, &live};
+    const size_t lds = (int64_t)P.thr_pad.size() <= kPatLdsThresholds ? P.thr_pad.size() * sizeof(float) : 0;
+    hipError_t e = hipModuleLaunchKernel(M->jit->patterns, (unsigned)((n + 255) / 256), 1, 1, 256, 1, 1,
+                                         (unsigned)lds, s, pargs, nullptr);
+    if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(patterns)");
+  }
   const float *t2 = bg->d_xtab.as<float>();
   int live = 1;
   void *args[] = {(void *)&pat, &n, (void *)&t2, &iv, &ldiv, &live};

@@ -100,7 +100,10 @@ def test_iv_source_matches_the_layout(wdf, which):
     src = wdf.iv_source(ens)
     sets = _path_feature_sets(ens)
     assert len(re.findall(r"\+= v\.", src)) == sum(len(s) * (len(s) - 1) for s in sets)
-    assert src.count('extern "C"') == (F + 3) // 4
+    assert len(re.findall(r"void wdf_iv_spec_\d+\(", src)) == (F + 3) // 4
+    # the pattern kernel stores every group's pattern, XOR-ed with its right turns
+    assert "void wdf_patterns_spec(" in src
+    assert len(re.findall(r"pat\[\(i64\)\d+ \* n \+ row\] = ", src)) == len(sets)
     writes = re.findall(r"o\[\(i64\)(\d+) \* ldo\] = (\S+);", src)
     assert sorted(int(k) for k, _ in writes) == list(range(F * F))
     for k, v in writes:
