@@ -314,29 +314,42 @@ __device__ __forceinline__ void quantize_rows(const float *__restrict__ T, const
                                               int nf, int bits, uint32_t *__restrict__ out) {
   const uint32_t nan_code = 1u << (bits - 1);
   const int64_t r0 = (int64_t)blockIdx.x * kQuantRows;
-  for (int64_t r = r0 + threadIdx.x; r < r0 + kQuantRows && r < n; r += 256) {
-    float x[4];
-    int p[4];
+  const int64_t r1 = r0 + kQuantRows < n ? r0 + kQuantRows : n;
+  // two rows per thread and iteration (r and r + 256; the second re-reads the
+  // first when past the end and is not stored), so that their loads and
+  // searches overlap
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 512) {
+    const int64_t rb = r + 256 < r1 ? r + 256 : r;
+    float x[2][4];
+    int p[2][4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      x[k] = k < nf ? X[(int64_t)(f0 + k) * ldx + r] : 0.f;
-      p[k] = 0;
+      x[0][k] = k < nf ? X[(int64_t)(f0 + k) * ldx + r] : 0.f;
+      x[1][k] = k < nf ? X[(int64_t)(f0 + k) * ldx + rb] : 0.f;
+      p[0][k] = p[1][k] = 0;
     }
     for (int sidx = cmax - 1; sidx >= 0; --sidx) {
-      // the four searches load unconditionally (a feature past its last step
+      // the searches load unconditionally (a feature past its last step
       // re-reads its own first threshold and ignores it), so the loads overlap
       const int step = 1 << sidx;
-      float t[4];
+      float t[2][4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t[k] = T[sidx < c[k] ? off[k] + p[k] + step - 1 : off[k]];
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) p[k] += (sidx < c[k] && t[k] <= x[k]) ? step : 0;
+        for (int k = 0; k < 4; ++k) t[h][k] = T[sidx < c[k] ? off[k] + p[h][k] + step - 1 : off[k]];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p[h][k] += (sidx < c[k] && t[h][k] <= x[h][k]) ? step : 0;
     }
-    uint32_t word = 0;
+    uint32_t word[2] = {0u, 0u};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (k < nf) word |= (x[k] != x[k] ? nan_code : (uint32_t)p[k]) << (k * bits);
-    out[r] = word;
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < nf) word[h] |= (x[h][k] != x[h][k] ? nan_code : (uint32_t)p[h][k]) << (k * bits);
+    out[r] = word[0];
+    if (rb != r) out[rb] = word[1];
   }
 }
 
