@@ -116,9 +116,12 @@ def _groups_per_feature(ens):
 
 def test_iv_many_groups_per_feature(wdf, ctx):
     """200 depth-4 trees over 3 of 8 features: each feature lies on more than
-    a thousand group paths (long work lists, runs of many items per partner)."""
+    a thousand group paths (long work lists, many units per feature) and has
+    more than 127 distinct thresholds, so ranks are 16-bit (word selects in
+    the generated pattern code)."""
     ens = synth.make_ensemble(synth.ModelSpec(200, 4, 4, 0.0, 8, feature_pool=3), synth.DataSpec(8, False, 0.0), 11)
     assert _groups_per_feature(ens).max() > 512
+    assert "WORD_1" in wdf.iv_source(ens)
     rng = np.random.default_rng(5)
     X = rng.normal(size=(8, 70)).astype(np.float32)
     B = rng.normal(size=(8, 41)).astype(np.float32)
