@@ -917,7 +917,7 @@ std::string gen_iv(const wdf_model *M) {
   o << kPreamble << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
   static const char *C[4] = {"x", "y", "z", "w"};
   for (int c = 0; c * kIvPerKernel < F; ++c) {
-    o << "extern \"C\" __global__ __launch_bounds__(256) void " << iv_kernel_name(c)
+    o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void " << iv_kernel_name(c)
       << "(const unsigned char* __restrict__ pat, i64 n, const float* __restrict__ t2, float* __restrict__ out, "
          "i64 ldo, int live) {\n"
       << "  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;\n"
@@ -934,23 +934,40 @@ std::string gen_iv(const wdf_model *M) {
       o << "  case " << i - c * kIvPerKernel << ": {\n";
       for (int j = 0; j < F; ++j)
         if (partner[(size_t)j]) o << "    float a" << j << " = 0.f;\n";
-      // `live` is always 1: the branches split the code into basic blocks of
-      // kIvBatch units, so that the scheduler does not hoist all of a case's
-      // loads to its top (registers)
-      for (int k = u0; k < u1; ++k) {
-        const IvUnit &u = M->iv_units[(size_t)k];
-        const int64_t E = (int64_t)1 << u.depth;
-        if ((k - u0) % kIvBatch == 0) o << "    if (live) {\n";
-        o << "    { const u32 p = pat[(i64)" << u.group << " * n + rr]; const vf4* t = (const vf4*)(t2 + " << u.dst
-          << ") + p;";
-        for (int pl = 0; 4 * pl < u.cnt; ++pl) {
-          o << " { const vf4 v = t[" << pl * E << "];";
-          for (int cc = 0; cc < 4 && 4 * pl + cc < u.cnt; ++cc)
-            o << " a" << M->iv_unit_partners[(size_t)k][(size_t)(4 * pl + cc)] << " += v." << C[cc] << ";";
-          o << " }";
+      // Units in batches of kIvBatch, one basic block each (`live` is always
+      // 1: the branches keep the scheduler from hoisting all of a case's loads
+      // to its top).  A batch's block loads the next batch's patterns (pn*)
+      // before its own table reads, which use the patterns loaded one block
+      // earlier (pc*).
+      auto load_patterns = [&](int k0, const char *dst) {
+        for (int k = k0; k < std::min(u1, k0 + kIvBatch); ++k)
+          o << "    " << dst << (k - k0) << " = pat[(i64)" << M->iv_units[(size_t)k].group << " * n + rr];\n";
+      };
+      if (u0 < u1) {
+        o << "    u32 pc0";
+        for (int b = 1; b < kIvBatch; ++b) o << ", pc" << b;
+        for (int b = 0; b < kIvBatch; ++b) o << ", pn" << b;
+        o << ";\n";
+        load_patterns(u0, "pc");
+      }
+      for (int k0 = u0; k0 < u1; k0 += kIvBatch) {
+        o << "    if (live) {\n";
+        if (k0 + kIvBatch < u1) load_patterns(k0 + kIvBatch, "pn");
+        for (int k = k0; k < std::min(u1, k0 + kIvBatch); ++k) {
+          const IvUnit &u = M->iv_units[(size_t)k];
+          const int64_t E = (int64_t)1 << u.depth;
+          o << "    { const vf4* t = (const vf4*)(t2 + " << u.dst << ") + pc" << (k - k0) << ";";
+          for (int pl = 0; 4 * pl < u.cnt; ++pl) {
+            o << " { const vf4 v = t[" << pl * E << "];";
+            for (int cc = 0; cc < 4 && 4 * pl + cc < u.cnt; ++cc)
+              o << " a" << M->iv_unit_partners[(size_t)k][(size_t)(4 * pl + cc)] << " += v." << C[cc] << ";";
+            o << " }";
+          }
+          o << " }\n";
         }
-        o << " }\n";
-        if ((k - u0) % kIvBatch == kIvBatch - 1 || k + 1 == u1) o << "    }\n";
+        if (k0 + kIvBatch < u1)
+          for (int b = 0; b < std::min(kIvBatch, u1 - k0 - kIvBatch); ++b) o << "    pc" << b << " = pn" << b << ";\n";
+        o << "    }\n";
       }
       o << "    if (row < n) {\n";
       for (int j = 0; j < F; ++j)
