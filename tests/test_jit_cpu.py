@@ -59,6 +59,18 @@ def test_gather_counts_match_the_layout(wdf):
         assert f"phi[{f} * ldphi + row]" in pairs
 
 
+@pytest.mark.parametrize("which,bound", [("small", 1024), ("mid", 1024), ("uneven", 512)])
+def test_histogram_launch_bound(wdf, which, bound):
+    """The histogram kernel is compiled for 1024-thread blocks when paths have
+    at most six positions and rows at most 32 rank words (95 VGPRs at the
+    paper shape), else for 512; its strides come from blockDim, so any
+    multiple of 64 threads up to the bound may be launched."""
+    src = wdf.specialised_source(synth.WORKLOADS[which].ensemble(), kernel=wdf.KERNEL_SPECIALISED)
+    assert f"__launch_bounds__({bound}) void wdf_hist_spec(" in src
+    hist = src[:src.index("#define NT ")]
+    assert "blockDim.x" in hist and "i += 512" not in hist and "i += 1024" not in hist
+
+
 def _path_feature_sets(ens):
     """Distinct features on the path of every leaf group (a pair of sibling
     leaves, or a leaf whose sibling is an inner node)."""
