@@ -115,18 +115,25 @@ int make_plan(wdf_model *M) {
   }
   // LDS slot of every histogram bin: bin p of a group of depth d sits at
   // slot s with lanes of a half-wave on distinct banks (see CountGen); perm
-  // maps a slot back to its bin
+  // maps a slot back to its bin.  Below a right turn at path position k < 6
+  // the histogram kernel keeps the left child's lane masks, so there a lane
+  // counts the bin of the lane with bit k flipped: the group's bins are
+  // XOR-permuted by its right turns (bit reversed, as lane bits map to
+  // pattern bits).
   P.perm.assign((size_t)M->hist_size, 0);
   for (const Group &g : M->groups) {
-    const int d = g.depth;
+    const int d = g.depth, dl = std::min(d, 6);
+    uint32_t flip = 0;  // right turns at positions k < 6, as pattern bits of the lane part
+    for (int k = 0; k < dl; ++k)
+      if (M->path[(size_t)g.path_off + k].dir) flip |= 1u << (dl - 1 - k);
     for (uint32_t s = 0; s < (1u << d); ++s) {
       uint32_t p;
       if (d < 6) {
-        p = s;
+        p = s ^ flip;
       } else {
         const uint32_t lo = s & 63u, j = s >> 6;
         const uint32_t v = ((lo << 1) | (lo >> 5)) & 63u;  // undo the rotate-right of the lane part
-        p = (v << (d - 6)) | j;
+        p = ((v ^ flip) << (d - 6)) | j;
       }
       P.perm[(size_t)(g.hist_off + s)] = (uint32_t)(g.hist_off + p);
     }
@@ -435,23 +442,20 @@ struct CountGen {
       return std::string(tag) + std::to_string(id) + "_" + std::to_string(r) + (h ? "h" : "l");
     };
     if (level < 6) {
-      // one three-input op per half: acc & (S ^ E) (truth table 0x60) for the
-      // left child, acc & ~(S ^ E) (0x90) for the right child
+      // one three-input op per half: acc & (S ^ E) (truth table 0x60).  The
+      // right child's masks, acc & ~(S ^ E), are the left child's in the lane
+      // with bit `level` flipped, so the right subtree keeps the left masks
+      // and its groups' bins are permuted instead (perm, built with the plan)
       const std::string E = "E" + std::to_string(level);
       for (size_t r = 0; r < acc.size(); ++r) {
-        if (need_l) {
+        if (need_l || need_r) {
           left.push_back({var("L", r, 0), var("L", r, 1)});
           o << "const u32 " << left.back().lo << " = __builtin_amdgcn_bitop3_b32(" << acc[r].lo << ", " << sl << ", " << E
             << ", 0x60), " << left.back().hi << " = __builtin_amdgcn_bitop3_b32(" << acc[r].hi << ", " << sh << ", "
             << E << ", 0x60);\n";
         }
-        if (need_r) {
-          right.push_back({var("R", r, 0), var("R", r, 1)});
-          o << "const u32 " << right.back().lo << " = __builtin_amdgcn_bitop3_b32(" << acc[r].lo << ", " << sl << ", "
-            << E << ", 0x90), " << right.back().hi << " = __builtin_amdgcn_bitop3_b32(" << acc[r].hi << ", " << sh
-            << ", " << E << ", 0x90);\n";
-        }
       }
+      right = left;
     } else {
       // deeper positions: both values of the bit, as replicas 2r (bit 0) and 2r+1 (bit 1)
       for (size_t r = 0; r < acc.size(); ++r) {
