@@ -137,7 +137,13 @@ int wdf_model_specialised(const wdf_model *model);
  * enqueued on `hip_stream` (NULL = the HIP null stream) and the call
  * returns after it finishes, so B may be freed on return.  The summary owns
  * all device state that wdf_explain needs (histograms, tables, workspace).
- * Errors: INVALID_ARG, OOM, DEVICE. */
+ * The first interaction summary of a model with specialised kernels also
+ * generates and compiles the model's interaction kernels (tens of seconds for
+ * 100 depth-6 trees); when they cannot be built (a model too large for them,
+ * a failed compile) the summary uses the generic interaction kernel
+ * (wdf_bg_specialised tells which).
+ * Errors: INVALID_ARG, UNSUPPORTED (interaction kinds: more than 65535 groups
+ * or features), OOM, DEVICE. */
 int wdf_background_load(wdf_model *model, const float *B, int64_t m, int64_t ldb, int b_on_device,
                         int values, void *hip_stream, wdf_bg **out);
 

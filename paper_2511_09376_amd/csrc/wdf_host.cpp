@@ -720,9 +720,9 @@ extern "C" int wdf_background_load(wdf_model *M, const float *B, int64_t m, int6
   if (bg->iv) {
     int rc_iv;
     if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
-    if (M->jit) {  // the specialised interaction kernel, unless the model is too large for it
+    if (M->jit) {  // the specialised interaction kernels; the generic one when they cannot be built
       rc_iv = jit_build_iv(M);
-      if (rc_iv != WDF_OK && rc_iv != WDF_E_UNSUPPORTED) return rc_iv;
+      if (rc_iv == WDF_E_OOM || rc_iv == WDF_E_DEVICE) return rc_iv;
       bg->iv_spec = rc_iv == WDF_OK;
     }
   }
@@ -877,9 +877,9 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   if (bg->iv) {
     int rc_iv;
     if ((rc_iv = prepare_iv(M, values - WDF_SHAPLEY_IV))) return rc_iv;
-    if (M->jit) {  // the specialised interaction kernel, unless the model is too large for it
+    if (M->jit) {  // the specialised interaction kernels; the generic one when they cannot be built
       rc_iv = jit_build_iv(M);
-      if (rc_iv != WDF_OK && rc_iv != WDF_E_UNSUPPORTED) return rc_iv;
+      if (rc_iv == WDF_E_OOM || rc_iv == WDF_E_DEVICE) return rc_iv;
       bg->iv_spec = rc_iv == WDF_OK;
     }
   }
