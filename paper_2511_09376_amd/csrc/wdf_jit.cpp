@@ -305,6 +305,7 @@ struct Gen {
   }
 
   std::function<void(int64_t unit, const std::string &p)> on_quad;  // null: no quads
+  std::function<void()> on_tree_end;                                 // before a tree's block closes
 
   void test(int64_t nd, const std::string &pout, const std::string &pin) {
     const int f = M->feature[(size_t)nd];
@@ -352,6 +353,7 @@ struct Gen {
       // block per tree, which keeps instruction selection time linear
       o << "if (live) {\n";
       node(root, "zero");
+      if (on_tree_end) on_tree_end();
       o << "}\n";
     }
   }
@@ -628,6 +630,8 @@ void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char
   }
 }
 
+constexpr int kGatherBatch = 4;  // explain units whose table reads are in flight together
+
 std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   const JitPlan &P = M->jp;
   const int F = M->n_features;
@@ -681,6 +685,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   emit_rank_words(o, M, used, P.thr_in_lds);
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
+  o << "  float sink = 0.f;  // unused table components (zeros)\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
   if (!thr_hi) o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n";
   o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
@@ -691,28 +696,43 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
       o << "  stage_copy(tab + " << t0 << ", lds + " << ((1 - buf) * P.stage_floats) << ", " << n16 << ");\n";
     }
     const int64_t sbase = P.xunits[(size_t)unit_of[(size_t)S[s].first]].dst;
-    // one 16-byte read per float4 plane returns four values of the entry;
+    // One 16-byte read per float4 plane returns four values of the entry;
     // value v adds to the feature of its path position when that position is
-    // the feature's first on the path.  The empty asm takes all four lanes of
-    // the read, so a plane with unused components is not narrowed to an 8- or
-    // 12-byte read, which costs more LDS cycles per value on random addresses.
+    // the feature's first on the path.  Components that add to no feature
+    // (zeros in the tables) add to `sink`, so that no read is narrowed to an
+    // 8- or 12-byte one (more LDS cycles per value on random addresses).  The
+    // reads of kGatherBatch units are issued before their adds, with a
+    // scheduling barrier between, so that that many are in flight (the
+    // compiler otherwise reads, waits and adds one unit at a time).
+    std::string pending;  // adds of the units whose reads are issued
+    int npending = 0, greg = 0;
+    auto flush = [&]() {
+      if (!npending) return;
+      o << "__builtin_amdgcn_sched_barrier(0);\n" << pending;
+      pending.clear();
+      npending = 0;
+    };
     auto gather = [&](const XUnit &x, const std::string &p, const std::vector<const PathNode *> &pos) {
       const int64_t E = (int64_t)1 << (x.depth + x.quad);
-      o << "{ const vf4* t = (const vf4*)(lds + " << (buf * P.stage_floats + (x.dst - sbase)) << ") + " << p << ";";
       static const char *C[4] = {"x", "y", "z", "w"};
+      std::ostringstream adds;
       for (int j = 0; 4 * j < x.nv; ++j) {
         bool any = false;
         for (int c = 0; c < 4 && 4 * j + c < x.nv; ++c) any = any || pos[(size_t)(4 * j + c)]->first;
         if (!any) continue;
-        o << " { vf4 a = t[" << j * E << "]; asm(\"\" : \"+v\"(a));";
-        for (int c = 0; c < 4 && 4 * j + c < x.nv; ++c) {
-          const PathNode *pn = pos[(size_t)(4 * j + c)];
-          if (pn->first) o << " f" << pn->feat << " += a." << C[c] << ";";
+        const std::string gv = "g" + std::to_string(greg++);
+        o << "const vf4 " << gv << " = ((const vf4*)(lds + " << (buf * P.stage_floats + (x.dst - sbase)) << ") + " << p
+          << ")[" << j * E << "];\n";
+        for (int c = 0; c < 4; ++c) {
+          const bool real = 4 * j + c < x.nv && pos[(size_t)(4 * j + c)]->first;
+          if (real) adds << " f" << pos[(size_t)(4 * j + c)]->feat << " += " << gv << "." << C[c] << ";";
+          else adds << " sink += " << gv << "." << C[c] << ";";
         }
-        o << " }";
       }
-      o << " }\n";
+      pending += adds.str() + "\n";
+      if (++npending == kGatherBatch) flush();
     };
+    gen.on_tree_end = flush;
     gen.on_group = [&](int64_t g, const std::string &p) {
       const Group &gr = M->groups[(size_t)g];
       std::vector<const PathNode *> pos;
@@ -742,6 +762,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
       if (touched[(size_t)f]) o << "  asm volatile(\"\" : \"+v\"(f" << f << "));\n";
     if (s + 1 < S.size()) o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
   }
+  o << "  if (live == 2) phi[row] = sink;  // never (live is 1): keeps the sink's reads whole\n";
   o << "  if (row < n) {\n";
   for (int f = 0; f < F; ++f) o << "    phi[" << f << " * ldphi + row] = " << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ";\n";
   o << "  }\n}\n";

@@ -47,8 +47,14 @@ def test_gather_counts_match_the_layout(wdf):
     ens = synth.WORKLOADS["small"].ensemble()
     pairs = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED | wdf.KERNEL_PAIRS))
     quads = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED))
-    pair_adds, quad_adds = len(re.findall(r"\+= a\.", pairs)), len(re.findall(r"\+= a\.", quads))
-    pair_reads, quad_reads = pairs.count("vf4 a = t["), quads.count("vf4 a = t[")
+    pair_adds = len(re.findall(r"f\d+ \+= g\d+\.", pairs))
+    quad_adds = len(re.findall(r"f\d+ \+= g\d+\.", quads))
+    pair_reads, quad_reads = pairs.count("const vf4 g"), quads.count("const vf4 g")
+    # every read's four components are consumed (features or the sink), in
+    # batches of reads issued before their adds
+    for src, reads in ((pairs, pair_reads), (quads, quad_reads)):
+        assert len(re.findall(r"(?:f\d+|sink) \+= g\d+\.[xyzw];", src)) == 4 * reads
+        assert "__builtin_amdgcn_sched_barrier(0);" in src
     assert pair_adds <= 10 * 8 * 4 and quad_adds <= 10 * 4 * 5
     assert quad_adds < pair_adds
     assert 0 < pair_reads <= 10 * 8 and 0 < quad_reads <= 10 * 4 * 2  # planes without a first position are skipped
