@@ -115,10 +115,19 @@ __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ group
   double *Hc = H + class_off[dp];
   for (uint32_t pp = threadIdx.x; pp < K; pp += blockDim.x) {
     double sl = 0.0, sr = 0.0;
-    for (uint32_t p = 0; p < (1u << d); ++p) {
-      const double c = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
-      if (merge_pattern(pn, d, dp, p) == pp) sl += c;
-      if (g.col_r >= 0 && merge_pattern(pn, d, dp, p ^ 1u) == pp) sr += c;
+    if (dp == d) {
+      // no repeated feature: the merge only permutes the bits, so exactly one
+      // pattern p merges to pp (and p ^ 1 for the right leaf)
+      uint32_t p = 0;
+      for (int k = 0; k < d; ++k) p |= ((pp >> (dp - 1 - pn[k].merge)) & 1u) << (d - 1 - k);
+      sl = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
+      if (g.col_r >= 0) sr = hist ? (double)hist[g.hist_off + (p ^ 1u)] : freq[g.hist_off + (p ^ 1u)];
+    } else {
+      for (uint32_t p = 0; p < (1u << d); ++p) {
+        const double c = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
+        if (merge_pattern(pn, d, dp, p) == pp) sl += c;
+        if (g.col_r >= 0 && merge_pattern(pn, d, dp, p ^ 1u) == pp) sr += c;
+      }
     }
     Hc[(int64_t)g.col_l * K + pp] = sl * (double)g.w_l * scale;
     if (g.col_r >= 0) Hc[(int64_t)g.col_r * K + pp] = sr * (double)g.w_r * scale;
