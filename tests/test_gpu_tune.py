@@ -37,12 +37,12 @@ def test_autotune_then_parity(wdf, ctx, workload):
     rep = model.autotune(Bd, Xd)
     assert rep["gather"] in ("pairs", "quads")
     assert rep["explain_ms"]["pairs"] > 0 and rep["explain_ms"]["quads"] > 0
-    best = min(rep["explain_ms"], key=rep["explain_ms"].get)
-    assert rep["gather"] == best
+    # the kept configurations are among the fastest measured (ties allowed)
+    assert rep["explain_ms"][rep["gather"]] <= min(rep["explain_ms"].values())
     swept = {f"{nt}x{r}" for nt in (512, 768, 1024) for r in (1, 2, 3, 4, 6, 8)}
     assert {f"512x{r}" for r in (1, 2, 3, 4, 6, 8)} <= set(rep["hist_ms"]) <= swept
-    fastest = min(rep["hist_ms"], key=rep["hist_ms"].get)
-    assert (rep["hist_threads"], rep["hist_rounds"]) == tuple(int(v) for v in fastest.split("x"))
+    kept = f"{rep['hist_threads']}x{rep['hist_rounds']}"
+    assert rep["hist_ms"][kept] <= min(rep["hist_ms"].values())
     assert model.specialised
     bg = wdf.Background(model, Bd)
     phi = bg.explain(Xd).cpu().numpy()
