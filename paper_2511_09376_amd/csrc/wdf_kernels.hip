@@ -107,12 +107,32 @@ __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ group
                                                  const double *__restrict__ freq, double scale,
                                                  const int64_t *__restrict__ class_off,
                                                  double *__restrict__ H) {
+  __shared__ uint32_t acc[2 * 256];  // merged counts of the left and right leaf (d' <= 8)
   const Group g = groups[blockIdx.x];
   if (g.depth == 0) return;
   const int d = g.depth, dp = g.dprime;
   const uint32_t K = 1u << dp;
   const PathNode *pn = path + g.path_off;
   double *Hc = H + class_off[dp];
+  if (dp < d && hist) {
+    // repeated features: scatter the integer counts onto their merged
+    // patterns (integer adds: exact in any order, so the result is
+    // deterministic), then weight
+    for (uint32_t i = threadIdx.x; i < 2 * K; i += blockDim.x) acc[i] = 0u;
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < (1u << d); p += blockDim.x) {
+      const uint32_t c = hist[g.hist_off + p];
+      if (!c) continue;
+      atomicAdd(&acc[merge_pattern(pn, d, dp, p)], c);
+      if (g.col_r >= 0) atomicAdd(&acc[K + merge_pattern(pn, d, dp, p ^ 1u)], c);
+    }
+    __syncthreads();
+    for (uint32_t pp = threadIdx.x; pp < K; pp += blockDim.x) {
+      Hc[(int64_t)g.col_l * K + pp] = (double)acc[pp] * (double)g.w_l * scale;
+      if (g.col_r >= 0) Hc[(int64_t)g.col_r * K + pp] = (double)acc[K + pp] * (double)g.w_r * scale;
+    }
+    return;
+  }
   for (uint32_t pp = threadIdx.x; pp < K; pp += blockDim.x) {
     double sl = 0.0, sr = 0.0;
     if (dp == d) {
