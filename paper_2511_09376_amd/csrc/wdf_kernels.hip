@@ -157,31 +157,50 @@ __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ group
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // S[col][r] = sum_k M[r][k] * H[col][k]  (M: R x K row-major, H: ncols x K).
-// One wave per 16x16 tile of the output, v_mfma_f64_16x16x4f64 over K.
+// One wave per 32x32 block of the output: 2 x 2 tiles of 16x16, each on
+// v_mfma_f64_16x16x4f64 over K; per step of 4 in K the wave loads two A and
+// two B fragments and issues four MFMAs (each fragment feeds two tiles).
 __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ M, const double *__restrict__ H,
                                                   double *__restrict__ S, int R, int K, int ncols) {
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int tiles_r = (R + 15) >> 4, tiles_c = (ncols + 15) >> 4;
-  if (wave >= tiles_r * tiles_c) return;  // uniform per wave
-  const int tr = wave % tiles_r, tc = wave / tiles_r;
+  const int blocks_r = (R + 31) >> 5, blocks_c = (ncols + 31) >> 5;
+  if (wave >= blocks_r * blocks_c) return;  // uniform per wave
+  const int br = wave % blocks_r, bc = wave / blocks_r;
   const int i = lane & 15, kq = lane >> 4;
-  const int arow = tr * 16 + i, bcol = tc * 16 + i;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  const int arow[2] = {br * 32 + i, br * 32 + 16 + i};
+  const int bcol[2] = {bc * 32 + i, bc * 32 + 16 + i};
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int kk = k0 + kq;
-    const double a = (arow < R && kk < K) ? M[(int64_t)arow * K + kk] : 0.0;
-    const double b = (bcol < ncols && kk < K) ? H[(int64_t)bcol * K + kk] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  // output element (row 4*t + lane/16, column lane%16) sits in acc[t]
-  const int ccol = tc * 16 + (lane & 15);
-  const int rbase = tr * 16 + (lane >> 4);
+    double a[2], b[2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int rr = rbase + 4 * t;
-    if (rr < R && ccol < ncols) S[(int64_t)ccol * R + rr] = acc[t];
+    for (int h = 0; h < 2; ++h) {
+      a[h] = (arow[h] < R && kk < K) ? M[(int64_t)arow[h] * K + kk] : 0.0;
+      b[h] = (bcol[h] < ncols && kk < K) ? H[(int64_t)bcol[h] * K + kk] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
   }
+  // in tile (x, y), output element (row 4*t + lane/16, column lane%16) sits in acc[x][y][t]
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int ccol = bc * 32 + 16 * y + (lane & 15);
+      const int rbase = br * 32 + 16 * x + (lane >> 4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int rr = rbase + 4 * t;
+        if (rr < R && ccol < ncols) S[(int64_t)ccol * R + rr] = acc[x][y][t];
+      }
+    }
 }
 
 // tab[g][k][p] = S_l[merge(k)][g(p)] + S_r[merge(k)][g(p ^ 1)] at the first
@@ -292,7 +311,7 @@ hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_g
 
 hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s) {
   if (ncols <= 0 || R <= 0) return hipSuccess;
-  const int waves = ((R + 15) / 16) * ((ncols + 15) / 16);
+  const int waves = ((R + 31) / 32) * ((ncols + 31) / 32);
   hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, M, H, S, R, K, ncols);
   return hipGetLastError();
 }
