@@ -29,6 +29,10 @@
  *   - Handles are owned by the library and freed by the matching destroy call.
  *     A context is bound to one HIP device.  Calls taking a `hip_stream`
  *     enqueue on it; NULL means the HIP null (legacy default) stream.
+ *     Loads, refreshes, debug copies and graph calls make the context's
+ *     device current on the calling thread; wdf_explain and wdf_explain_iv
+ *     do not (their launch path stays short), so call them with that device
+ *     current and a stream that belongs to it.
  */
 #ifndef WDF_H
 #define WDF_H
