@@ -163,11 +163,16 @@ def _check(rc: int):
     return rc
 
 
-def _stream_handle(stream):
+def _stream_handle(stream, device=None):
     import torch
     if stream is None:
-        stream = torch.cuda.current_stream()
+        stream = torch.cuda.current_stream(device)
     return C.c_void_p(stream.cuda_stream)
+
+
+def _on_device(X, device, what):
+    if X.device.index != device:
+        raise ValueError(f"{what} is on cuda:{X.device.index}, the context on cuda:{device}")
 
 
 def _colmajor_tensor(X, F, what):
@@ -353,15 +358,19 @@ class Background:
         import torch
         F = self.model.n_features
         X = _colmajor_tensor(X, F, "X")
+        dev = self.model.ctx.device
+        _on_device(X, dev, "X")
         n = X.shape[1]
         if out is None:
             out = torch.empty((F, n), dtype=torch.float32, device=X.device)
         else:
             out = _colmajor_tensor(out, F, "out")
+            _on_device(out, dev, "out")
         ldx = X.stride(0) if n else 0
         ldp = out.stride(0) if n else 0
-        _check(lib().wdf_explain(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldp,
-                                 _stream_handle(stream)))
+        with torch.cuda.device(dev):
+            _check(lib().wdf_explain(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldp,
+                                     _stream_handle(stream, dev)))
         return out
 
     def explain_iv(self, X, out=None, stream=None, workspace=None):
@@ -373,9 +382,12 @@ class Background:
         import torch
         F = self.model.n_features
         X = _colmajor_tensor(X, F, "X")
+        dev = self.model.ctx.device
+        _on_device(X, dev, "X")
         n = X.shape[1]
         if out is None:
             out = torch.empty((F, F, n), dtype=torch.float32, device=X.device)
+        _on_device(out, dev, "out")
         if out.shape != (F, F, n) or out.dtype != torch.float32 or (n > 1 and out.stride(2) != 1) or \
                 out.stride(1) != out.stride(0) // F:
             raise ValueError("out must be float32 [F, F, n] with rows contiguous")
@@ -384,8 +396,11 @@ class Background:
         need = self.iv_workspace_bytes(n)
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
-        _check(lib().wdf_explain_iv(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldo,
-                                    C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
+        _on_device(workspace, dev, "workspace")
+        with torch.cuda.device(dev):
+            _check(lib().wdf_explain_iv(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldo,
+                                        C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                        _stream_handle(stream, dev)))
         return out
 
     def iv_workspace_bytes(self, n: int) -> int:
