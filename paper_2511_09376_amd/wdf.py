@@ -186,6 +186,19 @@ def _colmajor_tensor(X, F, what):
 
 
 def _model_desc(ens, with_cover=True):
+    # The library reads node_offset[-1] entries of every node array: check the
+    # lengths here, where they are known.
+    off = np.asarray(ens.node_offset)
+    if off.ndim != 1 or off.shape[0] < 2:
+        raise ValueError("node_offset must be 1-D with n_trees + 1 >= 2 entries")
+    n_nodes = int(off[-1])
+    names = ["feature", "left", "right", "threshold", "value", "default_left"]
+    if with_cover and getattr(ens, "cover", None) is not None:
+        names.append("cover")
+    for name in names:
+        a = np.asarray(getattr(ens, name))
+        if a.ndim != 1 or a.shape[0] != n_nodes:
+            raise ValueError(f"{name} has shape {a.shape}, node_offset[-1] = {n_nodes} nodes")
     keep = [np.ascontiguousarray(ens.node_offset, np.int64), np.ascontiguousarray(ens.feature, np.int32),
             np.ascontiguousarray(ens.left, np.int32), np.ascontiguousarray(ens.right, np.int32),
             np.ascontiguousarray(ens.threshold, np.float32), np.ascontiguousarray(ens.value, np.float32),

@@ -165,3 +165,53 @@ def test_host_coefficient_matrices_match_the_oracle(wdf, d, values):
             vals = oracle.wdnf_values([(1.0, lits)], d, kind)
             expect[:, c, b] = vals
     np.testing.assert_allclose(M, expect, rtol=1e-12, atol=1e-15)
+
+
+def _one_tree(feature, left, right, n_features=2):
+    """A one-tree ensemble from raw node arrays (node 0 is the root)."""
+    n = len(feature)
+    return synth.Ensemble(n_features, np.array([0, n], np.int64), np.array(feature, np.int32),
+                          np.zeros(n, np.float32), np.array(left, np.int32), np.array(right, np.int32),
+                          np.arange(n, dtype=np.float32), np.zeros(n, np.uint8), np.ones(n, np.float64))
+
+
+def test_malformed_models_refused_on_the_host(wdf):
+    """Model validation runs on the host and refuses every malformed tree with
+    an error code (no GPU needed: the layout behind the generated source is
+    the one a model load builds)."""
+    ok = _one_tree([0, -1, -1], [1, -1, -1], [2, -1, -1])
+    assert "wdf_hist_spec" in wdf.specialised_source(ok)
+    cases = {
+        "feature out of range": (_one_tree([2, -1, -1], [1, -1, -1], [2, -1, -1]), wdf.E_INVALID_ARG, ">= n_features"),
+        "leaf with a child": (_one_tree([0, -1, -1], [1, 2, -1], [2, -1, -1]), wdf.E_INVALID_ARG, "leaf with children"),
+        "child out of range": (_one_tree([0, -1, -1], [1, -1, -1], [3, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
+        "root as a child": (_one_tree([0, -1, -1], [0, -1, -1], [2, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
+        "same child twice": (_one_tree([0, -1, -1], [1, -1, -1], [1, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
+        "node with two parents": (_one_tree([0, 1, 1, -1, -1], [1, 3, 3, -1, -1], [2, 4, 4, -1, -1]),
+                                  wdf.E_INVALID_ARG, "2 parents"),
+        # nodes 3 and 4 are each other's parent: one parent each, never reached from the root
+        "unreachable cycle": (_one_tree([0, -1, -1, 1, 1, -1, -1], [1, -1, -1, 4, 3, -1, -1],
+                                        [2, -1, -1, 5, 6, -1, -1]), wdf.E_INVALID_ARG,
+                              "unreachable"),
+    }
+
+    def chain(depth):
+        # inner nodes 0..depth-1 down the left; leaf `depth` ends the chain,
+        # leaves depth+1.. hang off the right of each inner node
+        feat = [0] * depth + [-1] * (depth + 1)
+        left = list(range(1, depth + 1)) + [-1] * (depth + 1)
+        right = [depth + 1 + k for k in range(depth)] + [-1] * (depth + 1)
+        return _one_tree(feat, left, right)
+
+    assert "wdf_hist_spec" in wdf.specialised_source(chain(8))  # the path limit itself (8 inner nodes)
+    cases["path deeper than the limit"] = (chain(9), wdf.E_UNSUPPORTED, "more than 8 inner nodes")
+    for name, (ens, code, text) in cases.items():
+        with pytest.raises(wdf.WdfError) as e:
+            wdf.specialised_source(ens)
+        assert e.value.code == code, name
+        assert text in str(e.value), (name, str(e.value))
+    # arrays shorter than node_offset claims never reach the library
+    short = _one_tree([0, -1, -1], [1, -1, -1], [2, -1, -1])
+    short.node_offset = np.array([0, 4], np.int64)
+    with pytest.raises(ValueError):
+        wdf.specialised_source(short)
