@@ -116,6 +116,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, I64, I32, I = C.c_void_p, C.c_int64, C.c_int32, C.c_int
         L.wdf_last_error.restype = C.c_char_p
+        L.wdf_last_error.argtypes = []
         L.wdf_create.argtypes = [I, C.POINTER(P)]
         L.wdf_destroy.argtypes = [P]
         L.wdf_model_load.argtypes = [P, P, I, C.POINTER(P)]

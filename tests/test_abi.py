@@ -30,8 +30,33 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(wdf.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, f"missing exports: {missing}"
-    assert set(wdf.EXPORTS) <= set(declared_functions())
+    assert set(wdf.EXPORTS) == set(declared_functions())
     assert wdf.lib().wdf_last_error() == b""
+
+
+def test_binding_types_follow_the_header():
+    """Every declared function has its argument count and return width in the
+    binding (a 64-bit return read as int would truncate sizes)."""
+    from paper_2511_09376_amd import wdf
+    if not os.path.exists(wdf.LIB_PATH):
+        pytest.skip("libwdf.so not built")
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    L = wdf.lib()
+    decls = re.findall(r"^\s*((?:const\s+)?[a-z_0-9]+(?:\s*\*)?)\s*(wdf_[a-z_]+)\s*\(([^)]*)\)\s*;", text, flags=re.M)
+    assert {n for _, n, _ in decls} == set(declared_functions())
+    for ret, name, args in decls:
+        fn = getattr(L, name)
+        n_args = 0 if args.strip() in ("", "void") else args.count(",") + 1
+        assert fn.argtypes is not None and len(fn.argtypes) == n_args, name
+        ret = ret.replace(" ", "")
+        if ret == "int64_t":
+            assert fn.restype is ctypes.c_int64, name
+        elif ret == "int":
+            assert fn.restype in (ctypes.c_int, None) or fn.restype is ctypes.c_int32, name
+        elif ret == "void":
+            assert fn.restype in (None, ctypes.c_int), name
+        elif ret == "constchar*":
+            assert fn.restype is ctypes.c_char_p, name
 
 
 def test_product_path_does_not_touch_the_oracle():
