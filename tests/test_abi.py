@@ -66,3 +66,22 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "woodelf_oracle" not in src, f
+
+
+def test_missing_library_fails_loudly():
+    """Without libwdf.so every entry point raises: there is no fallback path."""
+    import subprocess
+    import sys
+    code = ("import paper_2511_09376_amd.wdf as w\n"
+            "w.LIB_PATH = '/nonexistent/libwdf.so'\n"
+            "from paper_2511_09376_amd import synth\n"
+            "for call in (lambda: w.Context(0), lambda: w.specialised_source(synth.WORKLOADS['small'].ensemble())):\n"
+            "    try:\n"
+            "        call()\n"
+            "    except ImportError as e:\n"
+            "        assert 'is missing' in str(e)\n"
+            "    else:\n"
+            "        raise SystemExit('no error')\n"
+            "print('refused')\n")
+    res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0 and res.stdout.strip() == "refused", res.stderr
