@@ -50,3 +50,15 @@ def test_more_than_one_gpu_is_refused():
                          text=True, timeout=120)
     assert res.returncode == 2
     assert "measures one GPU" in res.stderr and res.stdout == ""
+
+
+def test_cpu_baseline_leg(bench):
+    """The oracle leg of the bench line on a tiny workload: the documented keys,
+    a positive rate, the thread count it used, and a bounded sample."""
+    w = synth.WORKLOADS["small"]
+    ens, X, B = w.ensemble(), w.consumers(), w.background()
+    out = bench.cpu_baseline(ens, X, B, seconds_hint=0.2)
+    assert set(out) == {"value", "unit", "cores", "kind", "sample"}
+    assert out["kind"] == "oracle" and out["unit"] == "rows/s" and out["value"] > 0
+    assert 1 <= out["cores"] <= min(16, os.cpu_count() or 1, X.shape[1])
+    assert "background rows" in out["sample"]
