@@ -101,7 +101,7 @@ typedef struct {
   const int32_t *feature;       /* split feature, -1 for leaves */
   const int32_t *left;          /* local index of the left child, -1 for leaves */
   const int32_t *right;         /* local index of the right child, -1 for leaves */
-  const float *threshold;       /* x < threshold goes left */
+  const float *threshold;       /* x < threshold goes left; not NaN (+-inf allowed) */
   const float *value;           /* leaf value w_l (ignored for inner nodes) */
   const uint8_t *default_left;  /* NaN direction: nonzero = left */
   const double *cover;          /* training rows reaching each node (Section 8); may be NULL */
@@ -114,7 +114,8 @@ typedef struct {
  * _SPECIALISED, optionally OR-ed with WDF_KERNEL_PAIRS; with AUTO or
  * SPECIALISED the pattern/histogram/gather kernels are generated for this
  * ensemble and compiled with hipRTC (cached per source).
- * Errors: INVALID_ARG (cycles, bad child or feature index, n_features < 1),
+ * Errors: INVALID_ARG (cycles, bad child or feature index, a NaN threshold,
+ * n_features < 1),
  * UNSUPPORTED (a path with more than WDF_MAX_DEPTH inner nodes, more than
  * WDF_MAX_FEATURES features), COMPILE (SPECIALISED only), OOM, DEVICE. */
 int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out);

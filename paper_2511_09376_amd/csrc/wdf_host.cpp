@@ -255,6 +255,8 @@ int wdf::validate_and_layout(const wdf_model_desc *d, wdf_model *M) {
       if (f >= d->n_features)
         return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has feature %d >= n_features %d", t,
                          (long long)i, f, d->n_features);
+      if (std::isnan(d->threshold[base + i]))
+        return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has a NaN threshold", t, (long long)i);
       if (l <= 0 || r <= 0 || l >= nn || r >= nn || l == r)
         return set_error(WDF_E_INVALID_ARG, "model: tree %d node %lld has invalid children (%d, %d)", t,
                          (long long)i, l, r);

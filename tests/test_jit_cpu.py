@@ -175,6 +175,12 @@ def _one_tree(feature, left, right, n_features=2):
                           np.arange(n, dtype=np.float32), np.zeros(n, np.uint8), np.ones(n, np.float64))
 
 
+def _nan_threshold():
+    ens = _one_tree([0, -1, -1], [1, -1, -1], [2, -1, -1])
+    ens.threshold[0] = np.nan
+    return ens
+
+
 def test_malformed_models_refused_on_the_host(wdf):
     """Model validation runs on the host and refuses every malformed tree with
     an error code (no GPU needed: the layout behind the generated source is
@@ -184,6 +190,7 @@ def test_malformed_models_refused_on_the_host(wdf):
     cases = {
         "feature out of range": (_one_tree([2, -1, -1], [1, -1, -1], [2, -1, -1]), wdf.E_INVALID_ARG, ">= n_features"),
         "leaf with a child": (_one_tree([0, -1, -1], [1, 2, -1], [2, -1, -1]), wdf.E_INVALID_ARG, "leaf with children"),
+        "NaN threshold": (_nan_threshold(), wdf.E_INVALID_ARG, "NaN threshold"),
         "child out of range": (_one_tree([0, -1, -1], [1, -1, -1], [3, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
         "root as a child": (_one_tree([0, -1, -1], [0, -1, -1], [2, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
         "same child twice": (_one_tree([0, -1, -1], [1, -1, -1], [1, -1, -1]), wdf.E_INVALID_ARG, "invalid children"),
@@ -204,6 +211,9 @@ def test_malformed_models_refused_on_the_host(wdf):
         return _one_tree(feat, left, right)
 
     assert "wdf_hist_spec" in wdf.specialised_source(chain(8))  # the path limit itself (8 inner nodes)
+    inf = _one_tree([0, 1, -1, -1, -1], [1, 3, -1, -1, -1], [2, 4, -1, -1, -1])
+    inf.threshold[:2] = [np.inf, -np.inf]                       # infinite thresholds are valid splits
+    assert "wdf_hist_spec" in wdf.specialised_source(inf)
     cases["path deeper than the limit"] = (chain(9), wdf.E_UNSUPPORTED, "more than 8 inner nodes")
     for name, (ens, code, text) in cases.items():
         with pytest.raises(wdf.WdfError) as e:
