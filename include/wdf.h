@@ -87,7 +87,12 @@ typedef struct wdf_bg wdf_bg;
  * valid until the next wdf call on the same thread. */
 const char *wdf_last_error(void);
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
+/* Create a context on HIP device `device`: the library's handle for one
+ * gfx950 device and its private stream.  *out receives the handle, owned by
+ * the caller until wdf_destroy.  Destroy the context's models and summaries
+ * before the context: wdf_destroy frees only the context itself.
+ * Errors: INVALID_ARG (NULL out, no such device), UNSUPPORTED (not gfx950),
+ * OOM, DEVICE. */
 int wdf_create(int device, wdf_ctx **out);
 void wdf_destroy(wdf_ctx *ctx);
 
@@ -107,27 +112,35 @@ typedef struct {
   const double *cover;          /* training rows reaching each node (Section 8); may be NULL */
 } wdf_model_desc;
 
-/* Validate and copy an ensemble (the caller may free its arrays on return),
- * extract its root-to-leaf paths, pair sibling leaves, build the
- * pattern-to-coefficient matrices in double precision and upload everything to
- * the context's device.  `kernel` is one of WDF_KERNEL_AUTO, _GENERIC,
+/* Validate and copy an ensemble (Def. Decision Tree; the caller may free its
+ * arrays on return), extract its root-to-leaf paths (the cubes of the tree's
+ * WDNF form, Formula model_to_wdnf_equation), pair sibling leaves, build the
+ * pattern-to-coefficient matrices in double precision (Section 5's four rules
+ * valued by Formula shap_simplified_formula or banzhaf_simplified_formula,
+ * one matrix per distinct-feature count; Alg. 2) and upload everything to the
+ * context's device.  `kernel` is one of WDF_KERNEL_AUTO, _GENERIC,
  * _SPECIALISED, optionally OR-ed with WDF_KERNEL_PAIRS; with AUTO or
  * SPECIALISED the pattern/histogram/gather kernels are generated for this
  * ensemble and compiled with hipRTC (cached per source).
  * Errors: INVALID_ARG (cycles, bad child or feature index, a NaN threshold,
- * n_features < 1),
- * UNSUPPORTED (a path with more than WDF_MAX_DEPTH inner nodes, more than
- * WDF_MAX_FEATURES features), COMPILE (SPECIALISED only), OOM, DEVICE. */
+ * n_features < 1), UNSUPPORTED (a path with more than WDF_MAX_DEPTH inner
+ * nodes, more than WDF_MAX_FEATURES features), COMPILE (SPECIALISED only),
+ * OOM, DEVICE. */
 int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kernel, wdf_model **out);
 void wdf_model_destroy(wdf_model *model);
 
 /* Per-group description of the model's layout (for tests and tools).  A group
- * is a pair of sibling leaves or a single leaf whose sibling is an inner node.
- * Any array may be NULL.  Returns the number of groups (>= 0) or an error. */
+ * is a pair of sibling leaves or a single leaf whose sibling is an inner node;
+ * its root-to-leaf path is the cube of the tree's WDNF form (Formula
+ * model_to_wdnf_equation), shared by both siblings but for the last literal.
+ * Any array may be NULL; a non-NULL array is host memory of at least as many
+ * entries as there are groups (call once with all NULL to learn the count).
+ * Returns the number of groups (>= 0) or INVALID_ARG (NULL model). */
 int64_t wdf_model_groups(const wdf_model *model, int32_t *tree, int32_t *depth, int64_t *leaf_left,
                          int64_t *leaf_right, int64_t *hist_offset, int64_t *table_offset);
 
-/* 1 when the model runs the specialised kernels, 0 for the generic ones. */
+/* 1 when the model runs the specialised kernels, 0 for the generic ones or a
+ * NULL model.  Never fails. */
 int wdf_model_specialised(const wdf_model *model);
 
 /* Summarise a background set: decision patterns of every row at every group,
@@ -166,7 +179,10 @@ void wdf_bg_destroy(wdf_bg *bg);
  * NULL summary. */
 int wdf_bg_specialised(const wdf_bg *bg);
 
-/* phi[f * ldphi + r] = value of feature f for consumer row r, r < n.  X and phi
+/* Explain consumer rows against a summary (Section 7 step (g); Alg. 3): each
+ * row's decision pattern at every group (Def. Decision Pattern) selects one
+ * entry of each of the group's tables, and the entries add up per feature.
+ * phi[f * ldphi + r] = value of feature f for consumer row r, r < n.  X and phi
  * are device pointers (column-major), n >= 0, ldx >= n, ldphi >= n.  Every
  * feature row of phi in [0, n_features) is written (exact 0.0 for features no
  * path uses).  Asynchronous on `hip_stream`; the caller keeps X and phi alive
@@ -184,20 +200,24 @@ int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float 
  * for consumer r, symmetric in (i, j), diagonal 0.  The rows' patterns of
  * every group go to `workspace` (device memory of at least
  * wdf_explain_iv_workspace(bg, n) bytes, owned by the caller, not shared by
- * overlapping calls); then one wave per (64 rows, feature i, slice of 32
- * partner features j) adds the pair tables into per-lane LDS accumulators.
+ * overlapping calls); then one wave per (64 rows, feature i) adds the pair
+ * tables of i's partners j, selected by those patterns, into registers and
+ * stores row i of each row's matrix (kernels generated for the model, or a
+ * generic kernel walking i's (group, j) work list sorted by j).
  * Asynchronous on hip_stream; allocates nothing.
  * Errors: INVALID_ARG (NULL, sizes, small workspace, summary not of an
  * interaction kind), UNSUPPORTED (more than 65535 groups), DEVICE. */
 int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
                    void *workspace, size_t workspace_bytes, void *hip_stream);
-/* Workspace bytes wdf_explain_iv needs for n rows (one byte per group and row). */
+/* Workspace bytes wdf_explain_iv needs for n rows (one byte per group and
+ * row; at least 1).  Errors: INVALID_ARG (NULL summary, n < 0). */
 int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n);
 
 /* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
  * f(c) - base).  For a path-dependent summary: the cover-weighted mean.  After
  * a refresh (below) the value is read from the device: synchronise the
- * refresh's stream first. */
+ * refresh's stream first.  *out is host memory.
+ * Errors: INVALID_ARG (NULL argument), DEVICE. */
 int wdf_base_value(const wdf_bg *bg, double *out);
 
 /* Recompute a background summary in place from new background rows: the same
@@ -228,11 +248,16 @@ void wdf_graph_destroy(wdf_graph *g);
 
 /* Decision patterns (Def. Decision Pattern, group orientation: the left leaf
  * of a pair, the leaf itself for a single) of n device rows:
- * out[g * n + r], uint32, device pointer.  Synchronous. */
+ * out[g * n + r], uint32, device pointer of at least n * groups entries;
+ * X device [F][ldx >= n].  Synchronous.
+ * Errors: INVALID_ARG (NULL, n < 0, ldx < n), DEVICE. */
 int wdf_debug_patterns(const wdf_model *model, const float *X, int64_t n, int64_t ldx, uint32_t *out,
                        void *hip_stream);
-/* Copy the uint32 histograms (cap entries of host memory) / float tables /
- * double tables to the host.  Returns the number of entries or an error. */
+/* Copy the uint32 histograms (Section 7 step (d); cap entries of host
+ * memory) / the float tables (step (f)) to the host.  With host_out NULL,
+ * only the entry count is returned.  Returns the number of entries, or
+ * INVALID_ARG (NULL summary, cap too small, a path-dependent summary for the
+ * histograms) or DEVICE. */
 int64_t wdf_debug_histograms(const wdf_bg *bg, uint32_t *host_out, int64_t cap);
 int64_t wdf_debug_tables(const wdf_bg *bg, float *host_out, int64_t cap);
 
@@ -260,7 +285,11 @@ int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int kernel, int
  * workspace, and the kernels that add the pair tables of Table table_shap_iv /
  * Formula banzhaf_simplified_formula_interactions, laid out per (group,
  * feature) and interleaved by pattern.  Same buffer convention as
- * wdf_debug_specialised_source; needs no GPU. */
+ * wdf_debug_specialised_source; needs no GPU.  The source is written
+ * whatever the model's size (loads fall back to the generic kernel above
+ * 400k table loads and adds).  Errors: as for model validation (INVALID_ARG,
+ * UNSUPPORTED), UNSUPPORTED for more than 65535 groups or features or a
+ * feature with more than 32767 distinct thresholds, OOM. */
 int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, int64_t cap);
 
 /* ---- autotuning --------------------------------------------------------- */
