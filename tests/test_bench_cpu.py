@@ -62,3 +62,20 @@ def test_cpu_baseline_leg(bench):
     assert out["kind"] == "oracle" and out["unit"] == "rows/s" and out["value"] > 0
     assert 1 <= out["cores"] <= min(16, os.cpu_count() or 1, X.shape[1])
     assert "background rows" in out["sample"]
+
+
+def test_traffic_summary_matches_the_current_explain_kernel(bench):
+    """The committed HBM-traffic summary was taken on the explain kernel the
+    generator writes today (same source hash), so the bench line's `traffic`
+    is a measurement of this kernel and not of an earlier one."""
+    from paper_2511_09376_amd import wdf
+    if not os.path.exists(wdf.LIB_PATH):
+        pytest.skip("libwdf.so not built")
+    ens = synth.WORKLOADS["paper"].ensemble()
+    traffic = bench.measured_traffic(wdf, ens, "paper", "quads")
+    assert traffic is not None, ("profiles/explain_quads_paper_traffic.md was taken on another explain kernel: "
+                                 "measure FETCH_SIZE / WRITE_SIZE again")
+    # measured bytes against the algorithmic bytes of one launch (X read,
+    # phi written: 2 x 127 x 4 B per row over 3M rows, 3.05 GB): within 1.5x
+    algorithmic = 2 * 127 * 4 * 3_000_000
+    assert algorithmic <= traffic <= 1.5 * algorithmic
