@@ -325,7 +325,8 @@ typedef struct {
   uint64_t submitted, completed, rejected;
   uint64_t batches;           /* device launches */
   uint64_t rows;              /* rows explained */
-  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result on host */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result on host, over the most
+                                            * recent 1048576 completed requests */
   double busy_ms;             /* sum over batches of device time from copy-in to copy-out */
 } wdf_stats;
 

@@ -74,9 +74,12 @@ struct wdf_server {
   bool stop = false;
   std::thread worker;
 
-  // statistics
+  // statistics; latencies of the most recent kLatencyWindow requests (a
+  // ring once full), so that a long-running server's memory stays bounded
+  static constexpr size_t kLatencyWindow = size_t(1) << 20;
   uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, rows = 0;
   std::vector<double> latency_ms;
+  uint64_t latency_next = 0;  // ring position once the window is full
   double busy_ms = 0.0;
   int worker_error = WDF_OK;
 
@@ -135,7 +138,11 @@ void wdf_server::drain(Slot &s) {
   std::lock_guard<std::mutex> lock(mu);
   for (auto &r : s.reqs) {
     r->done = true;
-    latency_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+    const double ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
+    if (latency_ms.size() < kLatencyWindow)
+      latency_ms.push_back(ms);
+    else
+      latency_ms[(size_t)(latency_next++ % kLatencyWindow)] = ms;
     ++completed;
   }
   ++batches;
