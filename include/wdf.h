@@ -351,10 +351,17 @@ int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int que
  * Errors: INVALID_ARG (n outside 1..max_rows), BUSY (queue full). */
 int wdf_server_submit(wdf_server *srv, const float *X_host, int64_t n, int64_t ldx, float *phi_host,
                       uint64_t *ticket);
-/* Wait until the ticket completes (timeout_ms < 0: forever).  Errors: TIMEOUT,
- * INVALID_ARG (unknown ticket). */
+/* Wait until the ticket completes (timeout_ms < 0: forever).  A return other
+ * than TIMEOUT releases the ticket, so wait on every ticket until it does
+ * (the server holds each ticket's entry until then); a released ticket is
+ * unknown afterwards.  Errors: TIMEOUT, INVALID_ARG (unknown ticket), or the
+ * error of the ticket's batch (DEVICE). */
 int wdf_server_wait(wdf_server *srv, uint64_t ticket, int timeout_ms);
+/* Counters since creation and latency percentiles (nearest rank) into *out
+ * (host memory).  Errors: INVALID_ARG (NULL argument). */
 int wdf_server_stats(wdf_server *srv, wdf_stats *out);
+/* Explain the requests still queued, stop the worker and free the server.
+ * No other call on srv may run concurrently or follow. */
 void wdf_server_destroy(wdf_server *srv);
 
 #ifdef __cplusplus
