@@ -526,9 +526,10 @@ class Server:
         return t.value
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> int:
-        rc = _check(lib().wdf_server_wait(self.h, ticket, timeout_ms))
-        self._inflight.pop(ticket, None)
-        return rc
+        rc = lib().wdf_server_wait(self.h, ticket, timeout_ms)
+        if rc != E_TIMEOUT:            # any other return releases the ticket
+            self._inflight.pop(ticket, None)
+        return _check(rc)
 
     def stats(self) -> Stats:
         s = Stats()
