@@ -54,7 +54,7 @@ def lib():
         L.wo_leaf_info.restype = I64
         L.wo_leaf_path.argtypes = [P, I64, P, P, P]
         L.wo_patterns.argtypes = [P, P, I64, I64, P]
-        L.wo_histograms.argtypes = [P, P, I64, I64, P, P]
+        L.wo_histograms.argtypes = [P, P, I64, I64, P, P, C.c_int]
         L.wo_wdnf_eval.argtypes = [C.c_int, P, P, C.c_int, P]
         L.wo_wdnf_eval.restype = C.c_double
         L.wo_wdnf_values.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
@@ -141,13 +141,14 @@ def patterns(model: Model, X) -> np.ndarray:
     return out
 
 
-def histograms(model: Model, B):
+def histograms(model: Model, B, threads=8):
     """(hist uint64[total], offsets int64[n_leaves+1]); hist[off[l]:off[l+1]] are the
-    counts of background patterns of leaf l."""
+    counts of background patterns of leaf l (exact integers, the same for any
+    thread count)."""
     B = _colmajor(B)
     off = model.hist_offsets()
     hist = np.empty(int(off[-1]), np.uint64)
-    lib().wo_histograms(model.ref, _ptr(B), B.shape[1], B.shape[1], _ptr(hist), _ptr(off))
+    lib().wo_histograms(model.ref, _ptr(B), B.shape[1], B.shape[1], _ptr(hist), _ptr(off), int(threads))
     return hist, off
 
 
@@ -167,7 +168,9 @@ def bg_fourrule(model, Cm, Bm, kind=SHAPLEY, threads=8):
 
 
 def bg_walk(model, Cm, Bm, kind=SHAPLEY, threads=8):
-    """Same values as bg_fourrule, visiting only satisfiable cubes; phi[F][n]."""
+    """Same values as bg_fourrule, visiting only satisfiable cubes; phi[F][n].
+    With fewer rows than threads, each row's mean over the background is summed
+    in contiguous background ranges that are then added in order."""
     return _bg(lib().wo_bg_walk, model, Cm, Bm, kind, threads)
 
 

@@ -378,25 +378,76 @@ int wo_patterns(const wo_model *M, const float *X, int64_t n, int64_t ldx, uint3
 }
 
 /* Value counts: hist[hist_off[leaf] + p] = #{b : P[leaf][b] = p}, with
- * hist_off[leaf+1] - hist_off[leaf] = 2^depth(leaf).  hist is zeroed here. */
-int wo_histograms(const wo_model *M, const float *B, int64_t m, int64_t ldb, uint64_t *hist,
-                  const int64_t *hist_off) {
-  double *x = (double *)malloc(sizeof(double) * (size_t)M->n_features);
-  int64_t lbase = 0;
-  for (int t = 0; t < M->n_trees; ++t) {
-    int64_t nl = collect_paths(M, t, NULL);
-    wo_path *paths = (wo_path *)malloc(sizeof(wo_path) * (size_t)nl);
-    collect_paths(M, t, paths);
-    for (int64_t j = 0; j < nl; ++j)
-      memset(hist + hist_off[lbase + j], 0, sizeof(uint64_t) * ((size_t)1 << paths[j].depth));
-    for (int64_t r = 0; r < m; ++r) {
-      load_row(B, ldb, r, M->n_features, x);
-      for (int64_t j = 0; j < nl; ++j) hist[hist_off[lbase + j] + path_pattern(M, &paths[j], x)] += 1;
-    }
-    free(paths);
-    lbase += nl;
+ * hist_off[leaf+1] - hist_off[leaf] = 2^depth(leaf).  hist is zeroed here.
+ * Every background row is walked along every leaf's path (Def. Decision
+ * Pattern).  With threads > 1 the rows are split into contiguous ranges, each
+ * counted into its own integer histogram; the ranges' counts are then added.
+ * Integer counts are exact, so the result is the same for any thread count. */
+typedef struct {
+  const wo_model *M;
+  const float *B;
+  int64_t ldb, r0, r1, n_leaves, bins;
+  const wo_path *paths;       /* every leaf of every tree, in global leaf order */
+  const int64_t *hist_off;
+  uint64_t *out;              /* this range's histogram, bins entries */
+} hist_range_t;
+
+/* rows in blocks of 64, so that each leaf's path is read once per block */
+static void *hist_range(void *arg) {
+  hist_range_t *H = (hist_range_t *)arg;
+  const int F = H->M->n_features;
+  double *x = (double *)malloc(sizeof(double) * (size_t)F * 64);
+  memset(H->out, 0, sizeof(uint64_t) * (size_t)H->bins);
+  for (int64_t r0 = H->r0; r0 < H->r1; r0 += 64) {
+    const int64_t nb = H->r1 - r0 < 64 ? H->r1 - r0 : 64;
+    for (int64_t i = 0; i < nb; ++i) load_row(H->B, H->ldb, r0 + i, F, x + (size_t)i * (size_t)F);
+    for (int64_t j = 0; j < H->n_leaves; ++j)
+      for (int64_t i = 0; i < nb; ++i)
+        H->out[H->hist_off[j] + (int64_t)path_pattern(H->M, &H->paths[j], x + (size_t)i * (size_t)F)] += 1;
   }
   free(x);
+  return NULL;
+}
+
+int wo_histograms(const wo_model *M, const float *B, int64_t m, int64_t ldb, uint64_t *hist,
+                  const int64_t *hist_off, int threads) {
+  int64_t nl = 0;
+  for (int t = 0; t < M->n_trees; ++t) nl += collect_paths(M, t, NULL);
+  wo_path *paths = (wo_path *)malloc(sizeof(wo_path) * (size_t)(nl > 0 ? nl : 1));
+  int64_t lbase = 0;
+  for (int t = 0; t < M->n_trees; ++t) lbase += collect_paths(M, t, paths + lbase);
+  const int64_t bins = hist_off[nl];
+  if (threads < 1) threads = 1;
+  if (threads > 256) threads = 256;
+  if ((int64_t)threads > m) threads = m > 0 ? (int)m : 1;
+  hist_range_t R[256];
+  uint64_t *part = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(bins > 0 ? bins : 1) * (size_t)threads);
+  for (int i = 0; i < threads; ++i) {
+    R[i].M = M;
+    R[i].B = B;
+    R[i].ldb = ldb;
+    R[i].r0 = m * i / threads;
+    R[i].r1 = m * (i + 1) / threads;
+    R[i].n_leaves = nl;
+    R[i].bins = bins;
+    R[i].paths = paths;
+    R[i].hist_off = hist_off;
+    R[i].out = part + (size_t)i * (size_t)bins;
+  }
+  if (threads == 1) {
+    hist_range(&R[0]);
+  } else {
+    pthread_t th[256];
+    for (int i = 0; i < threads; ++i) pthread_create(&th[i], NULL, hist_range, &R[i]);
+    for (int i = 0; i < threads; ++i) pthread_join(th[i], NULL);
+  }
+  for (int64_t k = 0; k < bins; ++k) {
+    uint64_t c = 0;
+    for (int i = 0; i < threads; ++i) c += part[(size_t)i * (size_t)bins + (size_t)k];
+    hist[k] = c;
+  }
+  free(part);
+  free(paths);
   return 0;
 }
 
@@ -667,6 +718,13 @@ static void walk(walk_state *S, int64_t nd, int32_t *sp, int na, int32_t *sm, in
   }
 }
 
+/* Formula trival_bg averages over the background rows.  A task is one
+ * consumer row and one contiguous range ("part") of the background: it sums
+ * the row's cube values over that range into its own accumulator.  With at
+ * least as many rows as threads there is one part per row; with fewer rows
+ * the background is cut into enough parts to give every thread work.  The
+ * parts of a row are then added in range order, so the result depends only
+ * on the part count, never on the thread schedule. */
 typedef struct {
   const wo_model *M;
   const float *C;
@@ -674,70 +732,67 @@ typedef struct {
   const float *B;
   int64_t m, ldb;
   int kind;
-  double *phi;
-  int64_t ldphi;
+  int iv;          /* interaction values ([F][F] per row) instead of phi */
+  int64_t parts;   /* background ranges per consumer row */
+  int64_t width;   /* accumulator entries per task: F, or F * F */
+  double *acc;     /* [n][parts][width] */
 } walkrows_ctx;
 
-static void walk_row(void *vctx, int64_t r) {
+static void walk_task(void *vctx, int64_t task) {
   walkrows_ctx *X = (walkrows_ctx *)vctx;
   const wo_model *M = X->M;
-  int F = M->n_features;
+  const int F = M->n_features;
+  const int64_t r = task / X->parts, part = task % X->parts;
+  const int64_t k0 = X->m * part / X->parts, k1 = X->m * (part + 1) / X->parts;
   double *c = (double *)malloc(sizeof(double) * (size_t)F);
   double *b = (double *)malloc(sizeof(double) * (size_t)F);
-  double *acc = (double *)calloc((size_t)F, sizeof(double));
+  double *acc = X->acc + (size_t)task * (size_t)X->width;
   load_row(X->C, X->ldc, r, F, c);
   int32_t sp[WO_MAXD], sm[WO_MAXD];
-  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, acc, 0, NULL};
-  for (int64_t k = 0; k < X->m; ++k) {
+  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, X->iv ? NULL : acc, 0, X->iv ? acc : NULL};
+  for (int64_t k = k0; k < k1; ++k) {
     load_row(X->B, X->ldb, k, F, b);
     for (int t = 0; t < M->n_trees; ++t) {
       S.base = M->node_offset[t];
       walk(&S, S.base, sp, 0, sm, 0);
     }
   }
-  for (int f = 0; f < F; ++f) X->phi[(int64_t)f * X->ldphi + r] = acc[f];
-  free(acc);
   free(b);
   free(c);
+}
+
+static int walk_rows(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B, int64_t m,
+                     int64_t ldb, int kind, int iv, double *out, int64_t ldo, int threads) {
+  const int F = M->n_features;
+  if (threads < 1) threads = 1;
+  int64_t parts = 1;
+  if (n > 0 && n < threads) parts = (threads + n - 1) / n;
+  if (parts > m) parts = m > 0 ? m : 1;
+  const int64_t width = iv ? (int64_t)F * F : F;
+  double *acc = (double *)calloc((size_t)(n * parts * width > 0 ? n * parts * width : 1), sizeof(double));
+  if (!acc) return -1;
+  walkrows_ctx ctx = {M, C, ldc, B, m, ldb, kind, iv, parts, width, acc};
+  parallel_rows(n * parts, threads, walk_task, &ctx);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t q = 0; q < width; ++q) {
+      double v = 0.0;
+      for (int64_t p = 0; p < parts; ++p) v += acc[((size_t)r * (size_t)parts + (size_t)p) * (size_t)width + (size_t)q];
+      out[q * ldo + r] = v;
+    }
+  free(acc);
+  return 0;
 }
 
 int wo_bg_walk(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B, int64_t m,
                int64_t ldb, int kind, double *phi, int64_t ldphi, int threads) {
-  walkrows_ctx ctx = {M, C, ldc, B, m, ldb, kind, phi, ldphi};
-  parallel_rows(n, threads, walk_row, &ctx);
-  return 0;
-}
-
-static void iv_walk_row(void *vctx, int64_t r) {
-  walkrows_ctx *X = (walkrows_ctx *)vctx;
-  const wo_model *M = X->M;
-  int F = M->n_features;
-  double *c = (double *)malloc(sizeof(double) * (size_t)F);
-  double *b = (double *)malloc(sizeof(double) * (size_t)F);
-  double *acc = (double *)calloc((size_t)F * (size_t)F, sizeof(double));
-  load_row(X->C, X->ldc, r, F, c);
-  int32_t sp[WO_MAXD], sm[WO_MAXD];
-  walk_state S = {M, c, b, X->kind, 1.0 / (double)X->m, NULL, 0, acc};
-  for (int64_t k = 0; k < X->m; ++k) {
-    load_row(X->B, X->ldb, k, F, b);
-    for (int t = 0; t < M->n_trees; ++t) {
-      S.base = M->node_offset[t];
-      walk(&S, S.base, sp, 0, sm, 0);
-    }
-  }
-  for (int64_t q = 0; q < (int64_t)F * F; ++q) X->phi[q * X->ldphi + r] = acc[q];
-  free(acc);
-  free(b);
-  free(c);
+  return walk_rows(M, C, n, ldc, B, m, ldb, kind, 0, phi, ldphi, threads);
 }
 
 /* Background interaction values: iv[(i * F + j) * ldphi + r] for consumer r,
  * the pair (i, j) of features, diagonal 0. */
 int wo_bg_iv_walk(const wo_model *M, const float *C, int64_t n, int64_t ldc, const float *B, int64_t m,
                   int64_t ldb, int kind, double *iv, int64_t ldphi, int threads) {
-  walkrows_ctx ctx = {M, C, ldc, B, m, ldb, kind, iv, ldphi};
-  parallel_rows(n, threads, iv_walk_row, &ctx);
-  return 0;
+  return walk_rows(M, C, n, ldc, B, m, ldb, kind, 1, iv, ldphi, threads);
 }
 
 /* ------------------------------------------------------------------------ */
