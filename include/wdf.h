@@ -253,6 +253,16 @@ void wdf_graph_destroy(wdf_graph *g);
  * Errors: INVALID_ARG (NULL, n < 0, ldx < n), DEVICE. */
 int wdf_debug_patterns(const wdf_model *model, const float *X, int64_t n, int64_t ldx, uint32_t *out,
                        void *hip_stream);
+/* Time the MFMA contraction of a summary (Section 7 steps (e)-(f)): the
+ * FP64 GEMM launches S = M_{d'} H_{d'}, one per distinct-feature class, run
+ * `reps` times on hip_stream (after one untimed run) from the summary's
+ * current histograms, into private buffers (the summary is not changed).
+ * *ms receives the average time of one contraction (all classes), *flops its
+ * floating-point operations (2 R K per leaf column of a class with R x K
+ * coefficients).  Allocates its buffers; synchronises.  For measurement.
+ * Errors: INVALID_ARG (NULL, reps < 1), OOM, DEVICE. */
+int wdf_debug_time_contraction(const wdf_bg *bg, int reps, void *hip_stream, double *flops, float *ms);
+
 /* Copy the uint32 histograms (Section 7 step (d); cap entries of host
  * memory) / the float tables (step (f)) to the host.  With host_out NULL,
  * only the entry count is returned.  Returns the number of entries, or
@@ -316,6 +326,33 @@ typedef struct {
  * UNSUPPORTED (the model runs the generic kernels), COMPILE, OOM, DEVICE. */
 int wdf_model_autotune(wdf_model *model, const float *B, int64_t m, int64_t ldb, const float *X, int64_t n,
                        int64_t ldx, void *hip_stream, wdf_tuning *out);
+
+/* Apply a launch configuration measured earlier (by wdf_model_autotune, in
+ * this process or another, and kept by the caller) without measuring again:
+ * t->quads selects the explain gather (0 pair tables, 1 quad tables, -1 the
+ * current one; each variant is compiled once and cached), t->hist_threads (a multiple of 64 in
+ * [64, the launch bound the model's histogram kernel was compiled for]) and
+ * t->hist_rounds (1..64 blocks per CU over the launch) the histogram grid.
+ * The time fields are ignored.  No summary of the model may exist during the
+ * call.  Results do not depend on the configuration: the histograms are exact
+ * counts in any grid, and both gathers add the same table values.
+ * Errors: INVALID_ARG (NULL, a field out of range, summaries exist),
+ * UNSUPPORTED (the model runs the generic kernels), COMPILE, OOM, DEVICE. */
+int wdf_model_set_tuning(wdf_model *model, const wdf_tuning *t);
+
+/* Grid of the model's specialised histogram kernel (Section 7 step (d)) for a
+ * summary of m background rows in the current launch configuration, as the
+ * next load or refresh of m rows will launch it.  launch (host, 6 entries):
+ * [0] blocks per chunk, [1] chunks (groups whose counters share one LDS
+ * histogram), [2] threads per block, [3] 64-row tiles per block, [4] tiles in
+ * all (the last one ragged when 64 does not divide m), [5] tiles counted by
+ * the busiest wave (wave w of a block takes the block's tiles w, w + waves,
+ * ...).  chunk_group (host, chunks + 1 entries, may be NULL): chunk c counts
+ * the groups [chunk_group[c], chunk_group[c + 1]).  Returns the chunk count.
+ * For tests; needs no device work.  Errors: INVALID_ARG (NULL model or
+ * launch, m < 1, capacity below chunks + 1), UNSUPPORTED (generic kernels). */
+int64_t wdf_debug_hist_launch(const wdf_model *model, int64_t m, int64_t *launch, int64_t *chunk_group,
+                              int64_t cap);
 
 /* ---- serving: continuous batching of explain requests ------------------- */
 

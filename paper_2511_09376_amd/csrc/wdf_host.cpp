@@ -644,6 +644,25 @@ static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
   return WDF_OK;
 }
 
+// The MFMA products S = M_{d'} H_{d'} of every distinct-feature class d'
+// (Section 7 steps (e)-(f)): one FP64 GEMM launch per class present.  *flops
+// (when given) receives their floating-point operations, 2 R K per column.
+static int enqueue_gemms(wdf_model *M, const wdf_bg *bg, const double *H, double *S, hipStream_t s, double *flops) {
+  double f = 0.0;
+  for (int dp = bg->iv ? 2 : 1; dp <= WDF_MAX_DEPTH; ++dp) {
+    const ClassInfo &c = M->cls[dp];
+    if (c.ncols == 0) continue;
+    const int K = 1 << dp, R = (bg->iv ? dp * (dp - 1) / 2 : dp) * K;
+    const double *coef = bg->iv ? M->d_coef_iv[bg->values - WDF_SHAPLEY_IV][dp].as<double>()
+                                : M->d_coef[bg->values][dp].as<double>();
+    double *Sc = S + (bg->iv ? M->s_iv_class_off[dp] : c.s_off);
+    HIP_TRY(launch_gemm_f64(coef, H + c.h_off, Sc, R, K, c.ncols, s));
+    f += 2.0 * (double)R * (double)K * (double)c.ncols;
+  }
+  if (flops) *flops = f;
+  return WDF_OK;
+}
+
 // Columns, MFMA products per class, expansion into the gather tables (and the
 // explain tables), base value into *base: kernel launches only.
 static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
@@ -652,14 +671,8 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
   HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
                          M->d_hclass_off.as<int64_t>(), H, s));
   if (bg->iv) {  // pair products per class, then pair tables
-    const int kind = bg->values - WDF_SHAPLEY_IV;
-    for (int dp = 2; dp <= WDF_MAX_DEPTH; ++dp) {
-      const ClassInfo &c = M->cls[dp];
-      if (c.ncols == 0) continue;
-      const int K = 1 << dp, R = dp * (dp - 1) / 2 * K;
-      HIP_TRY(launch_gemm_f64(M->d_coef_iv[kind][dp].as<double>(), H + c.h_off, S + M->s_iv_class_off[dp], R, K,
-                              c.ncols, s));
-    }
+    int rc;
+    if ((rc = enqueue_gemms(M, bg, H, S, s, nullptr))) return rc;
     HIP_TRY(launch_expand_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_off.as<int64_t>(),
                              M->d_siv_class_off.as<int64_t>(), S, bg->d_tab.as<float>(), s));
     if (bg->iv_spec)  // interleaved tables of the specialised interaction kernel
@@ -668,12 +681,8 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
     HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
     return WDF_OK;
   }
-  for (int dp = 1; dp <= WDF_MAX_DEPTH; ++dp) {
-    const ClassInfo &c = M->cls[dp];
-    if (c.ncols == 0) continue;
-    const int K = 1 << dp, R = dp * K;
-    HIP_TRY(launch_gemm_f64(M->d_coef[bg->values][dp].as<double>(), H + c.h_off, S + c.s_off, R, K, c.ncols, s));
-  }
+  int rc;
+  if ((rc = enqueue_gemms(M, bg, H, S, s, nullptr))) return rc;
   HIP_TRY(launch_expand(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_sclass_off.as<int64_t>(), S,
                         bg->d_tab.as<float>(), nullptr, s));
   if (M->jit)  // explain tables of the specialised kernel
@@ -764,7 +773,12 @@ static int ensure_refresh_workspace(wdf_bg *bg) {
   if (!bg->own_S.ptr &&
       (rc = bg->own_S.alloc((size_t)std::max<int64_t>(bg->iv ? M->s_iv_total : M->s_total, 1) * sizeof(double))))
     return rc;
-  if (!bg->d_base.ptr && (rc = bg->d_base.alloc(sizeof(double)))) return rc;
+  if (!bg->d_base.ptr) {
+    // seeded with the load's base value, so that the value read back from the
+    // device is valid before the first refresh has run
+    if ((rc = bg->d_base.alloc(sizeof(double)))) return rc;
+    HIP_TRY(hipMemcpy(bg->d_base.ptr, &bg->base, sizeof(double), hipMemcpyHostToDevice));
+  }
   return WDF_OK;
 }
 
@@ -956,6 +970,42 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
   HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_item_off.as<int32_t>(),
                             M->d_iv_items.as<int2>(), bg->d_tab.as<float>(), X, n, ldx, (uint8_t *)workspace, iv, ldiv,
                             M->n_features, s));
+  return WDF_OK;
+}
+
+extern "C" int wdf_debug_time_contraction(const wdf_bg *bg, int reps, void *hip_stream, double *flops, float *ms) {
+  if (!bg || !flops || !ms || reps < 1)
+    return set_error(WDF_E_INVALID_ARG, "wdf_debug_time_contraction: NULL argument or reps < 1");
+  wdf_model *M = bg->model;
+  HIP_TRY(hipSetDevice(bg->device));
+  hipStream_t s = pick_stream(M->ctx, hip_stream);
+  // private columns and products: the summary's own state is left untouched
+  DevBuf H, S;
+  int rc;
+  if ((rc = H.alloc((size_t)std::max<int64_t>(M->h_total, 1) * sizeof(double)))) return rc;
+  if ((rc = S.alloc((size_t)std::max<int64_t>(bg->iv ? M->s_iv_total : M->s_total, 1) * sizeof(double)))) return rc;
+  const bool counts = !bg->pathdep;
+  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(),
+                         counts ? bg->d_hist.as<uint32_t>() : nullptr, counts ? nullptr : bg->d_hist.as<double>(),
+                         counts ? 1.0 / (double)bg->m : 1.0, M->d_hclass_off.as<int64_t>(), H.as<double>(), s));
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_error(e, "hipEventCreate");
+  }
+  rc = enqueue_gemms(M, bg, H.as<double>(), S.as<double>(), s, flops);  // warm-up
+  if (!rc && (e = hipEventRecord(a, s)) != hipSuccess) rc = hip_error(e, "hipEventRecord");
+  for (int r = 0; !rc && r < reps; ++r) rc = enqueue_gemms(M, bg, H.as<double>(), S.as<double>(), s, flops);
+  if (!rc && (e = hipEventRecord(b, s)) != hipSuccess) rc = hip_error(e, "hipEventRecord");
+  if (!rc && (e = hipEventSynchronize(b)) != hipSuccess) rc = hip_error(e, "hipEventSynchronize");
+  float t = 0.f;
+  if (!rc && (e = hipEventElapsedTime(&t, a, b)) != hipSuccess) rc = hip_error(e, "hipEventElapsedTime");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  *ms = t / (float)reps;
   return WDF_OK;
 }
 

@@ -192,6 +192,11 @@ int jit_source(wdf_model *M, bool do_compile, std::string &src);
 int validate_and_layout(const wdf_model_desc *d, wdf_model *M);
 // background histograms; `codes` holds P.words * m words of threshold ranks
 int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, uint32_t *codes, hipStream_t s);
+// grid of the specialised histogram kernel for m background rows
+struct HistLaunch {
+  int64_t blocks = 0, chunks = 0, threads = 0, tiles_per_block = 0, ntiles = 0;
+};
+HistLaunch hist_launch(const wdf_model *M, int64_t m);
 // Grow a workspace buffer to at least `bytes` (contents are not kept).
 int ws_reserve(DevBuf &buf, size_t bytes);
 int jit_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *phi, int64_t ldphi, hipStream_t s);

@@ -1114,19 +1114,31 @@ int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, 
   return WDF_OK;
 }
 
+HistLaunch hist_launch(const wdf_model *M, int64_t m) {
+  // one block per CU at a time (the LDS histogram); a whole number of rounds
+  // over the CUs, split evenly between the chunks.  Wave w of a block counts
+  // the block's tiles w, w + waves, w + 2 waves, ...
+  const JitPlan &P = M->jp;
+  HistLaunch L;
+  L.chunks = (int64_t)P.hist_chunks.size();
+  L.threads = P.nt_hist;
+  L.ntiles = (m + 63) / 64;
+  const int64_t waves = P.nt_hist / 64;
+  int64_t blocks = std::max<int64_t>(1, (int64_t)P.hist_rounds * M->ctx->n_cu / L.chunks);
+  blocks = std::min<int64_t>(blocks, (L.ntiles + waves - 1) / waves);
+  L.tiles_per_block = (L.ntiles + blocks - 1) / blocks;
+  L.blocks = (L.ntiles + L.tiles_per_block - 1) / L.tiles_per_block;
+  return L;
+}
+
 int jit_hist(wdf_model *M, const float *B, int64_t m, int64_t ldb, uint32_t *hist, uint32_t *codes, hipStream_t s) {
   const JitPlan &P = M->jp;
   hipError_t e = launch_quantize(B, m, ldb, M->n_features, P.d_thr_pad.as<float>(), P.d_pad_meta.as<int2>(), P.wide,
                                  P.words, codes, m, s);
   if (e != hipSuccess) return hip_error(e, "quantize");
-  // one block per CU at a time (the LDS histogram); a whole number of rounds
-  // over the CUs, split evenly between the chunks
-  const int chunks = (int)P.hist_chunks.size();
-  const int64_t ntiles = (m + 63) / 64;
-  int64_t blocks = std::max<int64_t>(1, (int64_t)P.hist_rounds * M->ctx->n_cu / chunks);
-  blocks = std::min<int64_t>(blocks, (ntiles + P.nt_hist / 64 - 1) / (P.nt_hist / 64));
-  int64_t tiles_per_block = (ntiles + blocks - 1) / blocks;
-  blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
+  const HistLaunch L = hist_launch(M, m);
+  const int chunks = (int)L.chunks;
+  int64_t blocks = L.blocks, tiles_per_block = L.tiles_per_block;
   const uint32_t *cp = codes;
   const uint32_t *perm = P.d_perm.as<uint32_t>();
   int64_t ldc = m;

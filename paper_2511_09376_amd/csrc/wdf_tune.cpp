@@ -120,3 +120,56 @@ extern "C" int wdf_model_autotune(wdf_model *M, const float *B, int64_t m, int64
   HIP_TRY(hipStreamSynchronize(s));
   return WDF_OK;
 }
+
+extern "C" int wdf_model_set_tuning(wdf_model *M, const wdf_tuning *t) {
+  if (!M || !t) return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: NULL argument");
+  if (!M->jit) return set_error(WDF_E_UNSUPPORTED, "wdf_model_set_tuning: the model runs the generic kernels");
+  if (M->n_bg.load() != 0)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: %d background summaries of this model exist",
+                     M->n_bg.load());
+  if (t->quads < -1 || t->quads > 1)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: quads must be -1, 0 or 1");
+  if (t->hist_threads < 64 || t->hist_threads % 64 || t->hist_threads > M->jp.hist_bound)
+    return set_error(WDF_E_INVALID_ARG,
+                     "wdf_model_set_tuning: hist_threads %d is not a multiple of 64 in [64, %d] (the compiled bound)",
+                     t->hist_threads, M->jp.hist_bound);
+  if (t->hist_rounds < 1 || t->hist_rounds > 64)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: hist_rounds %d outside [1, 64]", t->hist_rounds);
+  HIP_TRY(hipSetDevice(M->ctx->device));
+  if (t->quads >= 0 && (t->quads != 0) != M->jp.quads) {
+    const bool keep = M->jp.quads;
+    M->jp.quads = t->quads != 0;
+    int rc = jit_build(M);
+    if (rc) {
+      M->jp.quads = keep;
+      (void)jit_build(M);  // the previous programs are cached
+      return rc;
+    }
+  }
+  // a rebuild re-plans the model; the launch-time choices are set after it
+  M->jp.nt_hist = t->hist_threads;
+  M->jp.hist_rounds = t->hist_rounds;
+  return WDF_OK;
+}
+
+extern "C" int64_t wdf_debug_hist_launch(const wdf_model *M, int64_t m, int64_t *launch, int64_t *chunk_group,
+                                         int64_t cap) {
+  if (!M || !launch || m < 1) return set_error(WDF_E_INVALID_ARG, "wdf_debug_hist_launch: NULL argument or m < 1");
+  if (!M->jit) return set_error(WDF_E_UNSUPPORTED, "wdf_debug_hist_launch: the model runs the generic kernels");
+  const HistLaunch L = hist_launch(M, m);
+  const int64_t waves = L.threads / 64;
+  launch[0] = L.blocks;
+  launch[1] = L.chunks;
+  launch[2] = L.threads;
+  launch[3] = L.tiles_per_block;
+  launch[4] = L.ntiles;
+  launch[5] = (L.tiles_per_block + waves - 1) / waves;  // tiles of the busiest wave
+  if (chunk_group) {
+    if (cap < L.chunks + 1)
+      return set_error(WDF_E_INVALID_ARG, "wdf_debug_hist_launch: capacity %lld < %lld", (long long)cap,
+                       (long long)(L.chunks + 1));
+    for (int64_t c = 0; c < L.chunks; ++c) chunk_group[c] = M->jp.hist_chunks[(size_t)c].first;
+    chunk_group[L.chunks] = L.chunks ? M->jp.hist_chunks[(size_t)L.chunks - 1].second : 0;
+  }
+  return L.chunks;
+}

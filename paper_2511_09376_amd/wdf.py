@@ -101,8 +101,9 @@ EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_bg_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
     "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
-    "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables",
-    "wdf_debug_specialised_source", "wdf_debug_iv_source", "wdf_debug_coef_matrix", "wdf_model_autotune", "wdf_server_create",
+    "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables", "wdf_debug_time_contraction",
+    "wdf_debug_specialised_source", "wdf_debug_iv_source", "wdf_debug_coef_matrix", "wdf_model_autotune",
+    "wdf_model_set_tuning", "wdf_debug_hist_launch", "wdf_server_create",
     "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
 
@@ -140,6 +141,7 @@ def lib():
         L.wdf_debug_patterns.argtypes = [P, P, I64, I64, P, P]
         L.wdf_debug_histograms.argtypes = [P, P, I64]
         L.wdf_debug_histograms.restype = I64
+        L.wdf_debug_time_contraction.argtypes = [P, I, P, C.POINTER(C.c_double), C.POINTER(C.c_float)]
         L.wdf_debug_tables.argtypes = [P, P, I64]
         L.wdf_debug_tables.restype = I64
         L.wdf_debug_specialised_source.argtypes = [P, I, I, P, I64]
@@ -149,6 +151,9 @@ def lib():
         L.wdf_debug_coef_matrix.argtypes = [I, I, P, I64]
         L.wdf_debug_coef_matrix.restype = I64
         L.wdf_model_autotune.argtypes = [P, P, I64, I64, P, I64, I64, P, C.POINTER(Tuning)]
+        L.wdf_model_set_tuning.argtypes = [P, C.POINTER(Tuning)]
+        L.wdf_debug_hist_launch.argtypes = [P, I64, P, P, I64]
+        L.wdf_debug_hist_launch.restype = I64
         L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
         L.wdf_server_wait.argtypes = [P, C.c_uint64, I]
@@ -296,6 +301,27 @@ class Model:
                 "hist_ms": {f"{nt}x{r}": float(t.hist_ms[i][r]) for i, nt in enumerate((512, 768, 1024))
                             for r in range(1, 9) if t.hist_ms[i][r] >= 0}}
 
+    def set_tuning(self, tuning: dict):
+        """Apply a configuration returned by autotune() (here or in another
+        process: the dict round-trips through JSON) without measuring; only
+        its gather (kept when absent), hist_threads and hist_rounds are used."""
+        t = Tuning()
+        t.quads = {"quads": 1, "pairs": 0, None: -1}[tuning.get("gather")]
+        t.hist_threads = int(tuning["hist_threads"])
+        t.hist_rounds = int(tuning["hist_rounds"])
+        _check(lib().wdf_model_set_tuning(self.h, C.byref(t)))
+
+    def hist_launch(self, m: int) -> dict:
+        """Grid of the specialised histogram kernel for m background rows."""
+        launch = np.zeros(6, np.int64)
+        chunks = _check(lib().wdf_debug_hist_launch(self.h, int(m), launch.ctypes.data, None, 0))
+        groups = np.zeros(chunks + 1, np.int64)
+        _check(lib().wdf_debug_hist_launch(self.h, int(m), launch.ctypes.data, groups.ctypes.data, chunks + 1))
+        keys = ["blocks", "chunks", "threads", "tiles_per_block", "tiles", "tiles_per_wave"]
+        out = {k: int(v) for k, v in zip(keys, launch)}
+        out["chunk_groups"] = groups
+        return out
+
     def groups(self) -> dict:
         G = _check(lib().wdf_model_groups(self.h, None, None, None, None, None, None))
         a = dict(tree=np.empty(G, np.int32), depth=np.empty(G, np.int32), leaf_left=np.empty(G, np.int64),
@@ -427,6 +453,12 @@ class Background:
         if self.m and B.shape[1] != self.m:
             raise ValueError(f"refresh needs {self.m} background rows, got {B.shape[1]}")
         _check(lib().wdf_background_refresh(self.h, C.c_void_p(B.data_ptr()), B.stride(0), _stream_handle(stream)))
+
+    def time_contraction(self, reps: int = 20, stream=None) -> tuple:
+        """(ms, flops) of one MFMA contraction of this summary, averaged over reps."""
+        f, t = C.c_double(), C.c_float()
+        _check(lib().wdf_debug_time_contraction(self.h, reps, _stream_handle(stream), C.byref(f), C.byref(t)))
+        return float(t.value), float(f.value)
 
     def histograms(self) -> np.ndarray:
         n = _check(lib().wdf_debug_histograms(self.h, None, 0))

@@ -53,3 +53,54 @@ def expected_tables(omodel, groups, freq, off, kind):
             t += sr[:, np.arange(P) ^ 1]
         out[to: to + d * P] = t.ravel()
     return out
+
+
+def assert_histograms_equal(groups, h, ens, B, trees=None, threads=16, cache=None):
+    """Every group's histogram (uint32 counts from the library) equals the
+    oracle's per-leaf counts over background B, bit for bit: the left (or
+    single) leaf's bins directly, the right leaf's with the last pattern bit
+    flipped.  `trees`: only the groups of these trees (the oracle then walks a
+    sub-ensemble of them); None: every group.  `cache`: a dict that keeps the
+    oracle's counts per (B, trees) across calls.  Returns the groups checked."""
+    trees = None if trees is None else sorted(set(int(t) for t in trees))
+    sub = ens if trees is None else ens.subset(trees)
+    om = oracle.Model(sub)
+    key = (id(B), None if trees is None else tuple(trees))
+    if cache is not None and key in cache:
+        href, off = cache[key]
+    else:
+        href, off = oracle.histograms(om, B, threads=threads)
+        if cache is not None:
+            cache[key] = (href, off)
+    node, _, ltree = om.leaf_info()
+    # the sub-ensemble's node numbers -> the full ensemble's
+    src = np.arange(ens.n_trees) if trees is None else np.asarray(trees)
+    shift = np.asarray(ens.node_offset)[src] - np.asarray(sub.node_offset)[:-1]
+    index = {int(n) + int(shift[t]): i for i, (n, t) in enumerate(zip(node, ltree))}
+    keep = set(range(ens.n_trees)) if trees is None else set(trees)
+    checked = 0
+    for g in range(groups["depth"].size):
+        if int(groups["tree"][g]) not in keep:
+            continue
+        d = int(groups["depth"][g])
+        ho = int(groups["hist_offset"][g])
+        got = h[ho: ho + (1 << d)].astype(np.uint64)
+        li = index[int(groups["leaf_left"][g])]
+        np.testing.assert_array_equal(got, href[off[li]: off[li + 1]], err_msg=f"group {g} (left leaf)")
+        if groups["leaf_right"][g] >= 0:
+            ri = index[int(groups["leaf_right"][g])]
+            np.testing.assert_array_equal(got[np.arange(1 << d) ^ 1], href[off[ri]: off[ri + 1]],
+                                          err_msg=f"group {g} (right leaf)")
+        checked += 1
+    return checked
+
+
+def chunk_trees(groups, chunk_groups):
+    """The first and last tree of every histogram chunk (so that a check of
+    these trees covers every chunk of the histogram kernel and its edges)."""
+    trees = set()
+    for c in range(len(chunk_groups) - 1):
+        a, b = int(chunk_groups[c]), int(chunk_groups[c + 1])
+        trees.add(int(groups["tree"][a]))
+        trees.add(int(groups["tree"][b - 1]))
+    return sorted(trees)

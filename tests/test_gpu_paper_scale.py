@@ -2,10 +2,12 @@
 features) at its full size, in the launch configuration the benchmark times:
 the model autotuned on the workload, one summary allocated, refreshed in
 place by a replayed HIP graph, one explain launch replayed by a second graph;
-and interaction values of a 256k-row chunk against the full background.  Checked on properties that hold at any
-size (histogram invariants over all 5M rows, efficiency on sampled rows
-against oracle predictions) and on sampled rows against the oracle with the
-full background."""
+and interaction values of a 256k-row chunk against the full background.
+Checked on properties that hold at any size (histogram invariants over all
+5M rows, efficiency on sampled rows against oracle predictions), on sampled
+rows against the oracle with the full background, and bit for bit on the histograms of the first and last tree
+of every histogram chunk over all 5M rows (the kernel's tile loop as
+launched, dozens of tiles per wave)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -13,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2511_09376_amd import synth
-from tests.gpu_util import assert_phi_close
+from tests.gpu_util import assert_histograms_equal, assert_phi_close, chunk_trees
 
 torch = pytest.importorskip("torch")
 
@@ -69,6 +71,17 @@ def test_paper_scale_graph_step(wdf, paper_data):
         full = (1 << d) - 1
         reach[groups["tree"][g]] += int(hg[full]) + (int(hg[full ^ 1]) if groups["leaf_right"][g] >= 0 else 0)
     assert np.all(reach == m)
+    # the tile loop as launched (tiles per wave from the library's own grid
+    # arithmetic): the first and last tree of every histogram chunk, bit for
+    # bit against the oracle's per-leaf counts over all 5M rows
+    L = model.hist_launch(m)
+    print(f"[paper] histogram grid: {L['blocks']} blocks x {L['chunks']} chunks of {L['threads']} threads, "
+          f"{L['tiles_per_block']} tiles per block, up to {L['tiles_per_wave']} per wave", flush=True)
+    assert L["tiles_per_wave"] >= 4
+    trees = chunk_trees(groups, L["chunk_groups"])
+    print(f"[paper] oracle histograms of trees {trees}", flush=True)
+    n_checked = assert_histograms_equal(groups, bg.histograms(), ens, B, trees=trees)
+    print(f"[paper] {n_checked} groups bit-exact over {m} rows", flush=True)
     om = oracle.Model(ens)
     print("[paper] oracle predictions", flush=True)
     base_ref = _predict(om, B).mean()

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2511_09376_amd import synth
-from tests.gpu_util import assert_phi_close, leaf_maps
+from tests.gpu_util import assert_histograms_equal, assert_phi_close, chunk_trees, leaf_maps
 
 torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
@@ -109,3 +109,65 @@ def test_uneven_subset_parity(wdf, uneven, kname):
     ref = oracle.bg_walk(om, Xs, Bs, threads=16)
     err = assert_phi_close(got, ref)
     print(f"uneven {kname}: row-scaled error {err:.3e}")
+
+
+def test_uneven_tile_loop_512(wdf, uneven):
+    """Paths of up to eight positions compile the histogram kernel for
+    512-thread blocks.  Its tile loop at 60 013 background rows (a ragged last
+    tile), several tiles per wave, bit for bit against the oracle for every
+    group."""
+    w, ens, ctx, model, X, B = uneven
+    m = 60_013
+    model.set_tuning({"hist_threads": 512, "hist_rounds": 2})
+    L = model.hist_launch(m)
+    print(f"[uneven] histogram grid at {m} rows: {L['blocks']} blocks x {L['chunks']} chunks of {L['threads']} "
+          f"threads, {L['tiles_per_block']} tiles per block, up to {L['tiles_per_wave']} per wave", flush=True)
+    assert L["threads"] == 512 and L["tiles_per_wave"] >= 4 and m % 64
+    Bs = np.ascontiguousarray(B[:, :m])
+    bg = wdf.Background(model, torch.from_numpy(Bs).cuda())
+    groups = model.groups()
+    n = assert_histograms_equal(groups, bg.histograms(), ens, Bs)
+    assert n == groups["depth"].size
+    bg.close()
+
+
+@pytest.mark.timeout(900)
+def test_uneven_benchmark_launch(wdf, uneven):
+    """The uneven workload exactly as the benchmark runs it: the model
+    autotuned on the workload, one summary refreshed in place by a replayed
+    graph, one explain launch over all 500 trees replayed by a second graph.
+    Then, at the full size: the histograms of the first and last tree of every
+    histogram chunk bit for bit over all 1M background rows, and phi of 8
+    sampled consumer rows against the oracle with the full 1M-row
+    background."""
+    w, ens, ctx, model, X, B = uneven
+    m, n = B.shape[1], X.shape[1]
+    Xd, Bd = torch.from_numpy(X).cuda(), torch.from_numpy(B).cuda()
+    print("[uneven] autotune", flush=True)
+    tuning = model.autotune(Bd, Xd)
+    print(f"[uneven] tuning {tuning}", flush=True)
+    bg = wdf.Background(model, Bd)
+    phi = torch.empty_like(Xd)
+    g_bg, g_ex = wdf.Graph(bg, B=Bd), wdf.Graph(bg, Xd, phi)
+    for _ in range(2):
+        g_bg.launch()
+        g_ex.launch()
+    torch.cuda.synchronize()
+    groups = model.groups()
+    L = model.hist_launch(m)
+    print(f"[uneven] histogram grid: {L['blocks']} blocks x {L['chunks']} chunks of {L['threads']} threads, "
+          f"{L['tiles_per_block']} tiles per block, up to {L['tiles_per_wave']} per wave", flush=True)
+    assert L["tiles_per_wave"] >= 4
+    trees = chunk_trees(groups, L["chunk_groups"])
+    print(f"[uneven] oracle histograms of {len(trees)} trees over {m} rows", flush=True)
+    n_checked = assert_histograms_equal(groups, bg.histograms(), ens, B, trees=trees)
+    print(f"[uneven] {n_checked} groups bit-exact", flush=True)
+    rows = np.concatenate([np.random.default_rng(11).choice(n, 6, replace=False), [0, n - 1]])
+    got = phi[:, torch.from_numpy(rows).cuda()].cpu().numpy()
+    print(f"[uneven] oracle walk of {rows.size} rows against {m} background rows", flush=True)
+    ref = oracle.bg_walk(oracle.Model(ens), np.ascontiguousarray(X[:, rows]), B, threads=16)
+    err = assert_phi_close(got, ref)
+    print(f"[uneven] row-scaled error {err:.3e}", flush=True)
+    g_bg.close()
+    g_ex.close()
+    bg.close()
