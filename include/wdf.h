@@ -56,7 +56,10 @@ enum {
 };
 
 #define WDF_MAX_DEPTH 8       /* inner nodes on any root-to-leaf path */
-#define WDF_MAX_FEATURES 4096
+#define WDF_MAX_FEATURES 65535          /* features of a model (columns of X and B) */
+#define WDF_MAX_SPECIALISED_FEATURES 4096 /* the specialised kernels' limit (their rank words
+                                             cover every feature); larger models run the
+                                             generic kernels */
 
 /* Values computed from the cube of a (consumer, background) pattern pair. */
 enum {
@@ -122,6 +125,8 @@ typedef struct {
  * _SPECIALISED, optionally OR-ed with WDF_KERNEL_PAIRS; with AUTO or
  * SPECIALISED the pattern/histogram/gather kernels are generated for this
  * ensemble and compiled with hipRTC (cached per source).
+ * A model with more than WDF_MAX_SPECIALISED_FEATURES features runs the
+ * generic kernels (AUTO), or is refused with UNSUPPORTED (SPECIALISED).
  * Errors: INVALID_ARG (cycles, bad child or feature index, a NaN threshold,
  * n_features < 1), UNSUPPORTED (a path with more than WDF_MAX_DEPTH inner
  * nodes, more than WDF_MAX_FEATURES features), COMPILE (SPECIALISED only),

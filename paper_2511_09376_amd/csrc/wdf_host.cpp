@@ -421,6 +421,17 @@ static int upload_model(wdf_model *M) {
       }
     }
     if ((rc = upload(M->d_ratio, ratio, s))) return rc;
+    // the right leaf of a pair: its last ratio cover(right leaf) / cover(parent),
+    // 0 when no training row reached the parent (then it is not 1 minus the
+    // left leaf's, which is 0 as well)
+    std::vector<double> ratio_r(std::max<size_t>(M->groups.size(), 1), 0.0);
+    for (size_t gi = 0; gi < M->groups.size(); ++gi) {
+      const Group &g = M->groups[gi];
+      if (g.col_r < 0 || g.depth == 0) continue;
+      const double cp = M->cover[(size_t)M->path_nodes[(size_t)g.path_off + (size_t)g.depth - 1]];
+      ratio_r[gi] = cp > 0 ? M->cover[(size_t)M->group_leaf_r[gi]] / cp : 0.0;
+    }
+    if ((rc = upload(M->d_ratio_r, ratio_r, s))) return rc;
   }
   HIP_TRY(hipStreamSynchronize(s));
   return WDF_OK;
@@ -668,7 +679,8 @@ static int enqueue_gemms(wdf_model *M, const wdf_bg *bg, const double *H, double
 static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, const double *freq, double scale,
                             double *H, double *S, double *base, hipStream_t s) {
   const int64_t G = (int64_t)M->groups.size();
-  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, scale,
+  const double *freq_r = freq ? freq + M->hist_size : nullptr;  // right leaves' own frequencies
+  HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, hist, freq, freq_r, scale,
                          M->d_hclass_off.as<int64_t>(), H, s));
   if (bg->iv) {  // pair products per class, then pair tables
     int rc;
@@ -678,7 +690,7 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
     if (bg->iv_spec)  // interleaved tables of the specialised interaction kernel
       HIP_TRY(launch_ivtab(M->d_iv_units.as<IvUnit>(), (int64_t)M->iv_units.size(), bg->d_tab.as<float>(),
                            bg->d_xtab.as<float>(), s));
-    HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
+    HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, freq_r, hist ? 1.0 / (double)bg->m : 1.0, base, s));
     return WDF_OK;
   }
   int rc;
@@ -688,7 +700,7 @@ static int enqueue_contract(wdf_model *M, wdf_bg *bg, const uint32_t *hist, cons
   if (M->jit)  // explain tables of the specialised kernel
     HIP_TRY(launch_xtab(M->jp.d_xunits.as<XUnit>(), (int64_t)M->jp.xunits.size(), bg->d_tab.as<float>(),
                         bg->d_xtab.as<float>(), s));
-  HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, hist ? 1.0 / (double)bg->m : 1.0, base, s));
+  HIP_TRY(launch_base(M->d_groups.as<Group>(), G, hist, freq, freq_r, hist ? 1.0 / (double)bg->m : 1.0, base, s));
   return WDF_OK;
 }
 
@@ -901,9 +913,11 @@ extern "C" int wdf_pathdep_load(wdf_model *M, int values, void *hip_stream, wdf_
   }
   bg->pathdep = true;
   int rc;
-  if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(M->hist_size, 1) * sizeof(double)))) return rc;
+  // frequencies of the left (or single) leaves, then those of the right leaves
+  if ((rc = bg->d_hist.alloc((size_t)std::max<int64_t>(2 * M->hist_size, 1) * sizeof(double)))) return rc;
   HIP_TRY(launch_pd_freq(M->d_groups.as<Group>(), (int64_t)M->groups.size(), M->d_ratio.as<double>(),
-                         bg->d_hist.as<double>(), s));
+                         M->d_ratio_r.as<double>(), bg->d_hist.as<double>(), bg->d_hist.as<double>() + M->hist_size,
+                         s));
   if ((rc = contract(M, bg.get(), nullptr, bg->d_hist.as<double>(), 1.0, s))) return rc;
   ++M->n_bg;
   *out = bg.release();
@@ -987,7 +1001,8 @@ extern "C" int wdf_debug_time_contraction(const wdf_bg *bg, int reps, void *hip_
   const bool counts = !bg->pathdep;
   HIP_TRY(launch_columns(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), (int64_t)M->groups.size(),
                          counts ? bg->d_hist.as<uint32_t>() : nullptr, counts ? nullptr : bg->d_hist.as<double>(),
-                         counts ? 1.0 / (double)bg->m : 1.0, M->d_hclass_off.as<int64_t>(), H.as<double>(), s));
+                         counts ? nullptr : bg->d_hist.as<double>() + M->hist_size, counts ? 1.0 / (double)bg->m : 1.0,
+                         M->d_hclass_off.as<int64_t>(), H.as<double>(), s));
   hipEvent_t a = nullptr, b = nullptr;
   HIP_TRY(hipEventCreate(&a));
   hipError_t e = hipEventCreate(&b);

@@ -116,7 +116,7 @@ struct wdf_model {
   int64_t h_total = 0, s_total = 0;
 
   // device copies
-  wdf::DevBuf d_groups, d_path, d_hclass_off, d_sclass_off, d_ratio;
+  wdf::DevBuf d_groups, d_path, d_hclass_off, d_sclass_off, d_ratio, d_ratio_r;
   wdf::DevBuf d_coef[2][WDF_MAX_DEPTH + 1];  // [values][dprime]
 
   // model-specialised kernels
@@ -159,7 +159,8 @@ struct wdf_bg {
   bool iv = false;      // an interaction kind: pair tables in d_tab, no explain tables
   bool pathdep = false;
   double base = 0.0;
-  wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent)
+  wdf::DevBuf d_hist;   // uint32 counts (background) or double frequencies (path-dependent: the left or
+                        // single leaves' [hist_size], then the right leaves' [hist_size])
   wdf::DevBuf d_tab;    // float gather tables
   wdf::DevBuf d_xtab;   // explain tables of the specialised kernel (quads merged), or the
                         // interleaved interaction tables (iv_spec)

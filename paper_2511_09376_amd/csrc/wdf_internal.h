@@ -15,13 +15,15 @@ hipError_t launch_explain_generic(const Group *groups, const PathNode *path, int
 hipError_t launch_patterns(const Group *groups, const PathNode *path, int64_t n_groups, const float *X,
                            int64_t n, int64_t ldx, uint32_t *out, hipStream_t s);
 hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_groups, const uint32_t *hist,
-                          const double *freq, double scale, const int64_t *class_off, double *H, hipStream_t s);
+                          const double *freq, const double *freq_r, double scale, const int64_t *class_off, double *H,
+                          hipStream_t s);
 hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s);
 hipError_t launch_expand(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *s_class_off,
                          const double *S, float *tab, double *tab64, hipStream_t s);
 hipError_t launch_base(const Group *groups, int64_t n_groups, const uint32_t *hist, const double *freq,
-                       double scale, double *out, hipStream_t s);
-hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, double *freq, hipStream_t s);
+                       const double *freq_r, double scale, double *out, hipStream_t s);
+hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, const double *ratio_r,
+                          double *freq, double *freq_r, hipStream_t s);
 hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr_pad, const int2 *meta,
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s);
 hipError_t launch_expand_iv(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *iv_off,

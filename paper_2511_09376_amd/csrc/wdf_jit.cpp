@@ -55,6 +55,11 @@ namespace {
 int make_plan(wdf_model *M) {
   JitPlan &P = M->jp;
   const int F = M->n_features;
+  // a row's threshold ranks are packed for every feature (feature f in word
+  // f / per_word), so the rank words, the background codes and the generated
+  // code grow with F
+  if (F > WDF_MAX_SPECIALISED_FEATURES)
+    return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %d features exceeds %d", F, WDF_MAX_SPECIALISED_FEATURES);
   std::vector<std::vector<float>> per(F);
   for (int64_t i = 0; i < M->n_nodes; ++i) {
     const int32_t f = M->feature[(size_t)i];

@@ -100,12 +100,14 @@ __device__ __forceinline__ uint32_t merge_pattern(const PathNode *__restrict__ p
 
 // H_{d'}[col][p'] = w * scale * sum over patterns p merging to p' of count[p];
 // the right leaf of a pair sees count[p ^ 1] (its pattern is the left's with
-// the last bit flipped).  `counts` is uint32 (background) or double (freq).
+// the last bit flipped).  `counts` is uint32 (background) or double
+// frequencies (path-dependent: freq for the left or single leaf, freq_r for
+// the right leaf of a pair, each indexed by that leaf's own pattern).
 __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ groups,
                                                  const PathNode *__restrict__ path,
                                                  const uint32_t *__restrict__ hist,
-                                                 const double *__restrict__ freq, double scale,
-                                                 const int64_t *__restrict__ class_off,
+                                                 const double *__restrict__ freq, const double *__restrict__ freq_r,
+                                                 double scale, const int64_t *__restrict__ class_off,
                                                  double *__restrict__ H) {
   __shared__ uint32_t acc[2 * 256];  // merged counts of the left and right leaf (d' <= 8)
   const Group g = groups[blockIdx.x];
@@ -141,12 +143,15 @@ __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ group
       uint32_t p = 0;
       for (int k = 0; k < d; ++k) p |= ((pp >> (dp - 1 - pn[k].merge)) & 1u) << (d - 1 - k);
       sl = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
-      if (g.col_r >= 0) sr = hist ? (double)hist[g.hist_off + (p ^ 1u)] : freq[g.hist_off + (p ^ 1u)];
+      if (g.col_r >= 0) sr = hist ? (double)hist[g.hist_off + (p ^ 1u)] : freq_r[g.hist_off + p];
     } else {
       for (uint32_t p = 0; p < (1u << d); ++p) {
         const double c = hist ? (double)hist[g.hist_off + p] : freq[g.hist_off + p];
         if (merge_pattern(pn, d, dp, p) == pp) sl += c;
-        if (g.col_r >= 0 && merge_pattern(pn, d, dp, p ^ 1u) == pp) sr += c;
+        if (g.col_r >= 0) {
+          if (hist && merge_pattern(pn, d, dp, p ^ 1u) == pp) sr += c;
+          if (!hist && merge_pattern(pn, d, dp, p) == pp) sr += freq_r[g.hist_off + p];
+        }
       }
     }
     Hc[(int64_t)g.col_l * K + pp] = sl * (double)g.w_l * scale;
@@ -231,12 +236,13 @@ __global__ __launch_bounds__(256) void k_expand(const Group *__restrict__ groups
   }
 }
 
-// Base value: sum over groups of w_l * c[all ones] + w_r * c[all ones ^ 1],
-// times scale; one block, fixed reduction order (deterministic).
+// Base value: sum over groups of w_l * c[all ones] + w_r * c[all ones ^ 1]
+// (path-dependent: w_l * freq[all ones] + w_r * freq_r[all ones]), times
+// scale; one block, fixed reduction order (deterministic).
 __global__ __launch_bounds__(256) void k_base(const Group *__restrict__ groups, int64_t n_groups,
                                               const uint32_t *__restrict__ hist,
-                                              const double *__restrict__ freq, double scale,
-                                              double *__restrict__ out) {
+                                              const double *__restrict__ freq, const double *__restrict__ freq_r,
+                                              double scale, double *__restrict__ out) {
   __shared__ double part[256];
   double s = 0.0;
   for (int64_t gi = threadIdx.x; gi < n_groups; gi += 256) {
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(256) void k_base(const Group *__restrict__ groups, 
     const double cl = hist ? (double)hist[g.hist_off + all] : freq[g.hist_off + all];
     s += (double)g.w_l * cl;
     if (g.col_r >= 0) {
-      const double cr = hist ? (double)hist[g.hist_off + (all ^ 1u)] : freq[g.hist_off + (all ^ 1u)];
+      const double cr = hist ? (double)hist[g.hist_off + (all ^ 1u)] : freq_r[g.hist_off + all];
       s += (double)g.w_r * cr;
     }
   }
@@ -258,17 +264,27 @@ __global__ __launch_bounds__(256) void k_base(const Group *__restrict__ groups, 
   if (threadIdx.x == 0) out[0] = part[0] * scale;
 }
 
-// Section 8: freq[p] = prod over path positions of r (bit 1) or 1 - r (bit 0),
-// r = cover(next node on the path) / cover(node); one block per group.
-__global__ __launch_bounds__(256) void k_pd_freq(const Group *__restrict__ groups,
-                                                 const double *__restrict__ ratio, double *__restrict__ freq) {
+// Section 8: freq[p] = prod over the leaf's path positions of r (bit 1) or
+// 1 - r (bit 0), r = cover(next node on the path) / cover(node); one block per
+// group.  The right leaf of a pair gets its own vector along its own path
+// (freq_r, the last ratio ratio_r[group]): with cover(parent) = 0 both last
+// ratios are 0 and the right leaf's is not 1 minus the left's.
+__global__ __launch_bounds__(256) void k_pd_freq(const Group *__restrict__ groups, const double *__restrict__ ratio,
+                                                 const double *__restrict__ ratio_r, double *__restrict__ freq,
+                                                 double *__restrict__ freq_r) {
   const Group g = groups[blockIdx.x];
   const int d = g.depth;
   const double *r = ratio + g.path_off;
   for (uint32_t p = threadIdx.x; p < (1u << d); p += blockDim.x) {
-    double v = 1.0;
-    for (int k = 0; k < d; ++k) v *= ((p >> (d - 1 - k)) & 1u) ? r[k] : 1.0 - r[k];
+    double v = 1.0, vr = 1.0;
+    for (int k = 0; k < d; ++k) {
+      const bool bit = ((p >> (d - 1 - k)) & 1u) != 0;
+      const double rk = k + 1 < d || g.col_r < 0 ? r[k] : ratio_r[blockIdx.x];
+      v *= bit ? r[k] : 1.0 - r[k];
+      vr *= bit ? rk : 1.0 - rk;
+    }
     freq[g.hist_off + p] = v;
+    if (g.col_r >= 0) freq_r[g.hist_off + p] = vr;
   }
 }
 
@@ -302,9 +318,10 @@ hipError_t launch_patterns(const Group *groups, const PathNode *path, int64_t n_
 }
 
 hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_groups, const uint32_t *hist,
-                          const double *freq, double scale, const int64_t *class_off, double *H, hipStream_t s) {
+                          const double *freq, const double *freq_r, double scale, const int64_t *class_off, double *H,
+                          hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_columns, dim3((unsigned)n_groups), dim3(256), 0, s, groups, path, hist, freq, scale,
+  hipLaunchKernelGGL(k_columns, dim3((unsigned)n_groups), dim3(256), 0, s, groups, path, hist, freq, freq_r, scale,
                      class_off, H);
   return hipGetLastError();
 }
@@ -325,14 +342,15 @@ hipError_t launch_expand(const Group *groups, const PathNode *path, int64_t n_gr
 }
 
 hipError_t launch_base(const Group *groups, int64_t n_groups, const uint32_t *hist, const double *freq,
-                       double scale, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_base, dim3(1), dim3(256), 0, s, groups, n_groups, hist, freq, scale, out);
+                       const double *freq_r, double scale, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_base, dim3(1), dim3(256), 0, s, groups, n_groups, hist, freq, freq_r, scale, out);
   return hipGetLastError();
 }
 
-hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, double *freq, hipStream_t s) {
+hipError_t launch_pd_freq(const Group *groups, int64_t n_groups, const double *ratio, const double *ratio_r,
+                          double *freq, double *freq_r, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pd_freq, dim3((unsigned)n_groups), dim3(256), 0, s, groups, ratio, freq);
+  hipLaunchKernelGGL(k_pd_freq, dim3((unsigned)n_groups), dim3(256), 0, s, groups, ratio, ratio_r, freq, freq_r);
   return hipGetLastError();
 }
 

@@ -171,6 +171,48 @@ def test_mid_full_size_sampled_rows(wdf, ctx, mid, kname):
     assert np.all(got[unused] == 0.0)
 
 
+@pytest.mark.parametrize("kname", ["generic", "auto"])
+def test_mid_banzhaf_sampled_rows(wdf, ctx, mid, kname):
+    """Banzhaf values (Formula banzhaf_simplified_formula) of the 100-tree
+    depth-6 model over the full 100k background: sampled rows against the
+    oracle's walk with the full background; null players exactly 0."""
+    w, ens, X, B = mid
+    om = oracle.Model(ens)
+    model = _load(wdf, ctx, ens, kname)
+    bg = wdf.Background(model, _cuda(B), values=wdf.BANZHAF)
+    rows = np.concatenate([np.random.default_rng(12).choice(X.shape[1], 6, replace=False), [0, X.shape[1] - 1]])
+    got = bg.explain(_cuda(X[:, rows])).cpu().numpy()
+    ref = oracle.bg_walk(om, np.ascontiguousarray(X[:, rows]), B, kind=oracle.BANZHAF, threads=16)
+    err = assert_phi_close(got, ref)
+    print(f"mid Banzhaf ({kname}): row-scaled error {err:.3e}")
+    unused = np.setdiff1d(np.arange(ens.n_features), np.unique(ens.feature[ens.feature >= 0]))
+    assert np.all(got[unused] == 0.0)
+
+
+@pytest.mark.parametrize("kname", ["generic", "auto"])
+@pytest.mark.parametrize("values", ["shapley", "banzhaf"])
+def test_mid_path_dependent(wdf, ctx, mid, kname, values):
+    """Path-dependent values (Section 8, Formula eq:path_dependent_estimation)
+    of the 100-tree depth-6 model: the library's cover-product frequencies,
+    contraction and gather against the oracle's Alg. 3 form with its own
+    product-form frequencies (both pinned to coalition enumeration on the
+    small model), on sampled rows; null players exactly 0."""
+    w, ens, X, B = mid
+    om = oracle.Model(ens)
+    kind = oracle.SHAPLEY if values == "shapley" else oracle.BANZHAF
+    model = _load(wdf, ctx, ens, kname)
+    bg = wdf.Background(model, pathdep=True, values=kind)
+    rows = np.concatenate([np.random.default_rng(13).choice(X.shape[1], 30, replace=False), [0, X.shape[1] - 1]])
+    Xs = np.ascontiguousarray(X[:, rows])
+    got = bg.explain(_cuda(Xs)).cpu().numpy()
+    freq, off = oracle.pd_freq(om)
+    ref = oracle.woodelf_phi(om, Xs, freq, off, kind)
+    err = assert_phi_close(got, ref)
+    print(f"mid path-dependent {values} ({kname}): row-scaled error {err:.3e}")
+    unused = np.setdiff1d(np.arange(ens.n_features), np.unique(ens.feature[ens.feature >= 0]))
+    assert np.all(got[unused] == 0.0)
+
+
 # ---------------------------------------------------------------------------
 # Edge cases
 # ---------------------------------------------------------------------------
@@ -278,6 +320,59 @@ def test_path_dependent(wdf, ctx, kname, values):
     bg = wdf.Background(model, pathdep=True, values=kind)
     got = bg.explain(_cuda(X)).cpu().numpy()
     assert_phi_close(got, oracle.pd_bruteforce(oracle.Model(ens), X, kind))
+
+
+@pytest.mark.parametrize("kname", KERNELS)
+@pytest.mark.parametrize("values", ["shapley", "banzhaf"])
+def test_path_dependent_zero_cover_parent(wdf, ctx, kname, values):
+    """A leaf pair whose parent no training row reached: each leaf's
+    frequencies along its own path (0/0 read as 0), against the path-dependent
+    game by coalition enumeration."""
+    from tests.test_oracle import ZERO_COVER_COVERS, ZERO_COVER_TREE, zero_cover_case
+    M, C = zero_cover_case()
+    kind = oracle.SHAPLEY if values == "shapley" else oracle.BANZHAF
+    model = _load(wdf, ctx, ensemble([ZERO_COVER_TREE], 3, ZERO_COVER_COVERS), kname)
+    bg = wdf.Background(model, pathdep=True, values=kind)
+    got = bg.explain(_cuda(C)).cpu().numpy()
+    assert_phi_close(got, oracle.pd_bruteforce(M, C, kind))
+
+
+def test_most_features_generic(wdf, ctx):
+    """The ABI's feature limit, 65535 features, with splits spread over the
+    whole range: AUTO loads the generic kernels (the specialised ones take up
+    to 4096 features), SPECIALISED is refused; histograms bit for bit, phi
+    against the oracle walk, every feature no split uses exactly 0."""
+    F = 65535
+    feats = [0, 17, 4096, 40000, 65534, 31337, 65534]
+    tree = lambda k: ("split", feats[k % 7], 0.1 * k, k % 2,
+                      ("split", feats[(k + 1) % 7], -0.3, 0, ("leaf", 1.0 + k), ("leaf", -0.5)),
+                      ("split", feats[(k + 3) % 7], 0.2, 1,
+                       ("split", feats[(k + 5) % 7], 0.0, 0, ("leaf", 0.25 * k), ("leaf", 2.0)), ("leaf", -1.5)))
+    ens = ensemble([tree(k) for k in range(5)], F)
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((F, 300)).astype(np.float32)
+    X = rng.standard_normal((F, 7)).astype(np.float32)
+    B[40000, ::5] = np.nan
+    X[4096, 2] = np.nan
+    with pytest.raises(wdf.WdfError) as e:
+        wdf.Model(ctx, ens, wdf.KERNEL_SPECIALISED)
+    assert e.value.code == wdf.E_UNSUPPORTED
+    model = wdf.Model(ctx, ens, wdf.KERNEL_AUTO)
+    assert not model.specialised
+    bg = wdf.Background(model, _cuda(B))
+    om = oracle.Model(ens)
+    groups = model.groups()
+    left, right, _ = leaf_maps(om, groups)
+    h = bg.histograms()
+    href, off = oracle.histograms(om, B, threads=2)
+    for g in range(groups["depth"].size):
+        d = int(groups["depth"][g])
+        ho = int(groups["hist_offset"][g])
+        np.testing.assert_array_equal(h[ho: ho + (1 << d)], href[off[left[g]]: off[left[g] + 1]])
+    got = bg.explain(_cuda(X)).cpu().numpy()
+    assert_phi_close(got, oracle.bg_walk(om, X, B, threads=4))
+    unused = np.setdiff1d(np.arange(F), feats)
+    assert np.all(got[unused] == 0.0)
 
 
 # ---------------------------------------------------------------------------

@@ -225,3 +225,16 @@ def test_malformed_models_refused_on_the_host(wdf):
     short.node_offset = np.array([0, 4], np.int64)
     with pytest.raises(ValueError):
         wdf.specialised_source(short)
+
+
+def test_feature_limits(wdf):
+    """Models may have up to 65535 features; the specialised kernels, whose
+    threshold ranks are packed for every feature, take up to 4096 and refuse
+    more with UNSUPPORTED (a load with AUTO then runs the generic kernels);
+    65536 features are refused at validation."""
+    assert "wdf_hist_spec" in wdf.specialised_source(_one_tree([4095, -1, -1], [1, -1, -1], [2, -1, -1], 4096))
+    for F, where in ((4097, "specialised kernels: 4097 features"), (65535, "specialised kernels: 65535 features"),
+                     (65536, "65536 features exceeds the limit 65535")):
+        with pytest.raises(wdf.WdfError) as e:
+            wdf.specialised_source(_one_tree([F - 1, -1, -1], [1, -1, -1], [2, -1, -1], F))
+        assert e.value.code == wdf.E_UNSUPPORTED and where in str(e.value), (F, str(e.value))

@@ -376,6 +376,41 @@ def test_pd_tables_equal_pd_bruteforce(seed, kind):
                                atol=1e-12)
 
 
+ZERO_COVER_TREE = ("split", 0, 0.0, 0,
+                   ("split", 1, 0.5, 1,
+                    ("split", 2, -0.5, 0, ("leaf", 1.5), ("leaf", -2.0)),
+                    ("leaf", 0.75)),
+                   ("leaf", -1.0))
+# node order: root, B, A, leafA_l, leafA_r, leafB_r, leaf_root_r; no training
+# row reached A (the parent of a leaf pair), while its parent B had 60
+ZERO_COVER_COVERS = [[100.0, 60.0, 0.0, 0.0, 0.0, 60.0, 40.0]]
+
+
+def zero_cover_case():
+    M = oracle.Model(ensemble([ZERO_COVER_TREE], 3, ZERO_COVER_COVERS))
+    C = colmajor([[-1.0, 0.0, -1.0], [-1.0, 0.0, 0.0], [-1.0, 1.0, -1.0], [1.0, 0.0, -1.0], [-1.0, 0.0, 1.0]])
+    return M, C
+
+
+@pytest.mark.parametrize("kind", [oracle.SHAPLEY, oracle.BANZHAF])
+def test_pd_zero_cover_parent(kind):
+    """Formula eq:path_dependent_estimation along each leaf's own path, with
+    0/0 read as 0 at a node no training row reached, equals the path-dependent
+    game by coalition enumeration.  Deriving the right leaf's frequencies from
+    its sibling's (1 - r at the last position) would not: at a zero-cover
+    parent both last ratios are 0."""
+    M, C = zero_cover_case()
+    freq, off = oracle.pd_freq(M)
+    ref = oracle.pd_bruteforce(M, C, kind)
+    np.testing.assert_allclose(oracle.woodelf_phi(M, C, freq, off, kind), ref, atol=1e-12)
+    node, depth, _ = M.leaf_info()
+    left, right = [int(np.nonzero(node == n)[0][0]) for n in (3, 4)]
+    assert depth[left] == depth[right] == 3
+    sib = freq.copy()
+    sib[off[right]:off[right + 1]] = freq[off[left]:off[left + 1]][np.arange(8) ^ 1]
+    assert np.abs(oracle.woodelf_phi(M, C, sib, off, kind) - ref).max() > 1e-3
+
+
 def test_binomial_form_of_coefficients():
     # (|S+|-1)! |S-|! / |S|! equals 1 / (|S+| C(|S|, |S+|)) (Theorem simplified_shapely)
     for a in range(1, 9):
