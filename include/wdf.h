@@ -369,23 +369,47 @@ typedef struct {
   uint64_t rows;              /* rows explained */
   double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result on host, over the most
                                             * recent 1048576 completed requests */
-  double busy_ms;             /* sum over batches of device time from copy-in to copy-out */
+  double busy_ms;             /* device time of all batches, copy-in start to copy-out end */
+  double copy_in_ms, explain_ms, copy_out_ms;  /* busy_ms split into its three parts */
+  double pack_ms, unpack_ms;  /* host time packing requests into the slots' staging and
+                                 unpacking results (on the copy threads) */
+  double active_ms;           /* first submission to the latest completion */
+  int slots;                  /* batch slots the server holds */
+  int64_t batch_rows;         /* rows per batch slot */
 } wdf_stats;
 
-/* A server keeps bg resident and owns a worker thread and up to four batch
- * slots, each with pinned host staging, device buffers for X and phi, a stream
- * and events; the slots it creates are those that fit in mem_budget bytes
- * (4 * n_features * max_rows * 4 bytes each).  Queued requests of 1..max_rows
- * rows are admitted FIFO as slots free up: a batch packs the oldest requests
- * that fit in max_rows rows (one request per batch with
- * WDF_SERVE_ONE_PER_LAUNCH), is copied in, explained and copied out on its
- * slot's stream, so batches of different slots overlap on the device.  Each
- * result is bit-identical to wdf_explain on the same rows alone.  The server
- * must be destroyed before bg.  Errors: INVALID_ARG (budget below one slot,
- * max_rows or queue_cap < 1), OOM, DEVICE. */
+/* Server configuration. */
+typedef struct {
+  size_t mem_budget;  /* bytes of staging the server may hold: each batch slot takes
+                         4 * n_features * batch_rows * 4 (pinned host and device, X and phi);
+                         the server creates as many slots as fit, at most four */
+  int max_rows;       /* largest request, in rows (>= 1) */
+  int batch_rows;     /* rows per batch slot, max_rows .. 2^24; 0: max(max_rows, 65536) */
+  int queue_cap;      /* queued requests beyond which submit returns BUSY (>= 1) */
+  int flags;          /* WDF_SERVE_ONE_PER_LAUNCH, WDF_SERVE_START_PAUSED */
+  int copy_threads;   /* host threads that pack and unpack batches (0: 4; at most 64) */
+} wdf_server_config;
+
+/* A server keeps bg resident and owns a worker thread, copy threads and up to
+ * four batch slots, each with pinned host staging and device buffers for
+ * batch_rows rows of X and phi, a stream and events; the slots it creates are
+ * those that fit in cfg->mem_budget.  Queued requests of 1..max_rows rows are
+ * admitted FIFO as slots free up: a batch packs the oldest requests that fit
+ * in batch_rows rows, is copied in, explained (wdf_explain) and copied out on
+ * its slot's stream, so batches of different slots overlap on the device and
+ * with the packing of the next batch.  With WDF_SERVE_ONE_PER_LAUNCH the server
+ * is the plain form: one slot of max_rows rows, one request per launch, each
+ * copied in, explained and copied out before the next.  Each result is
+ * bit-identical to wdf_explain on the same rows alone.  The server must be
+ * destroyed before bg.  Errors: INVALID_ARG (NULL, budget below one slot,
+ * sizes out of range), OOM, DEVICE. */
 #define WDF_SERVE_ONE_PER_LAUNCH 1
-int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int queue_cap, int flags,
-                      wdf_server **out);
+#define WDF_SERVE_START_PAUSED 2   /* admit nothing until wdf_server_pause(srv, 0) */
+int wdf_server_create(const wdf_bg *bg, const wdf_server_config *cfg, wdf_server **out);
+/* Stop (paused != 0) or resume admitting queued requests into batches.
+ * Batches already launched complete; submissions keep queueing while paused
+ * (up to queue_cap).  Errors: INVALID_ARG (NULL server). */
+int wdf_server_pause(wdf_server *srv, int paused);
 /* Enqueue n rows of host X (column-major, ldx >= n); phi_host receives
  * [n_features][n] column-major float32 when the ticket completes.  Both stay
  * owned by the caller and must remain valid until wdf_server_wait has returned

@@ -1,25 +1,30 @@
 // Serving loop: continuous batching of explain requests over a resident
 // background summary.
 //
-// Requests (1..max_rows rows of caller-owned host data) wait in a FIFO queue.  A worker
-// thread owns a fixed set of slots, each with pinned host staging, device
-// buffers for X and phi, a stream and an event; the number of slots is what
-// the memory budget pays for.  Whenever a slot is free the worker packs the
-// oldest queued requests that fit in max_rows rows into it, copies the batch
-// in, runs wdf_explain and copies phi back, all asynchronously on the slot's
-// stream, so the batches of different slots overlap on the device.  A slot
-// whose event has completed is drained: each request's rows are copied to its
-// caller's buffer and its latency (submit to result on host) is recorded.
-// Every row is explained independently of the others in its batch, so a
-// request's result is bit-identical alone and in any mix.
+// Requests (1..max_rows rows of caller-owned host data) wait in a FIFO queue.
+// A worker thread owns a fixed set of batch slots, each with pinned host
+// staging and device buffers for batch_rows rows of X and phi, a stream and
+// events; the number of slots is what the memory budget pays for (at most
+// four).  Whenever a slot is free the worker takes the oldest queued requests
+// that fit in batch_rows rows, has the copy threads pack their rows into the
+// slot's staging, then copies the batch in, runs wdf_explain and copies phi
+// back, all asynchronously on the slot's stream, so the batches of different
+// slots overlap on the device and with the packing of the next batch.  A
+// slot whose last event has completed is drained: the copy threads unpack
+// each request's rows into its caller's buffer, and its latency (submit to
+// result on host) is recorded.  Every row is explained independently of the
+// others in its batch, so a request's result is bit-identical alone and in
+// any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -44,11 +49,80 @@ struct Request {
   int status = WDF_OK;
 };
 
+// Host threads that split a copy job into parts: run(parts, fn) calls
+// fn(0) .. fn(parts - 1) on the helpers and the calling thread and returns
+// when all have finished.
+class CopyPool {
+ public:
+  explicit CopyPool(int threads) {
+    for (int i = 1; i < threads; ++i) helpers_.emplace_back([this] { loop(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto &t : helpers_) t.join();
+  }
+  void run(int parts, const std::function<void(int)> &fn) {
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      fn_ = &fn;
+      parts_ = parts;
+      next_ = 0;
+      done_ = 0;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lock(mu_);
+    cv_done_.wait(lock, [&] { return done_ == parts_; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void work() {
+    for (;;) {
+      int p;
+      const std::function<void(int)> *fn;
+      {
+        std::lock_guard<std::mutex> lock(mu_);
+        if (!fn_ || next_ >= parts_) return;
+        p = next_++;
+        fn = fn_;
+      }
+      (*fn)(p);
+      std::lock_guard<std::mutex> lock(mu_);
+      if (++done_ == parts_) cv_done_.notify_all();
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lock(mu_);
+        cv_.wait(lock, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+    }
+  }
+  std::vector<std::thread> helpers_;
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  const std::function<void(int)> *fn_ = nullptr;
+  int parts_ = 0, next_ = 0, done_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 struct Slot {
-  float *hx = nullptr, *hphi = nullptr;  // pinned [F][max_rows]
-  float *dx = nullptr, *dphi = nullptr;  // device [F][max_rows]
+  float *hx = nullptr, *hphi = nullptr;  // pinned [F][batch_rows]
+  float *dx = nullptr, *dphi = nullptr;  // device [F][batch_rows]
   hipStream_t stream = nullptr;
-  hipEvent_t start = nullptr, done = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, copied in, explained, copied out
   std::vector<std::shared_ptr<Request>> reqs;
   int64_t rows = 0;
   bool busy = false;
@@ -61,17 +135,19 @@ struct wdf_server {
   const wdf_bg *bg = nullptr;
   int device = 0;
   int F = 0;
-  int64_t max_rows = 0;
+  int64_t max_rows = 0, batch_rows = 0;
   int queue_cap = 0;
   bool one_per_launch = false;
   std::vector<Slot> slots;
+  std::unique_ptr<CopyPool> pool;
+  int copy_parts = 1;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> pending;
   uint64_t next_ticket = 1, next_seq = 1;
-  bool stop = false;
+  bool stop = false, paused = false;
   std::thread worker;
 
   // statistics; latencies of the most recent kLatencyWindow requests (a
@@ -80,39 +156,59 @@ struct wdf_server {
   uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, rows = 0;
   std::vector<double> latency_ms;
   uint64_t latency_next = 0;  // ring position once the window is full
-  double busy_ms = 0.0;
+  double busy_ms = 0.0, copy_in_ms = 0.0, explain_ms = 0.0, copy_out_ms = 0.0;
+  double pack_ms = 0.0, unpack_ms = 0.0;
+  bool any_submit = false;
+  Clock::time_point first_submit, last_done;
   int worker_error = WDF_OK;
 
   void run();
   void launch(Slot &s);
   void drain(Slot &s);
+  // request offsets inside a slot's batch
+  static std::vector<int64_t> offsets(const Slot &s) {
+    std::vector<int64_t> off(s.reqs.size());
+    int64_t o = 0;
+    for (size_t i = 0; i < s.reqs.size(); ++i) off[i] = o, o += s.reqs[i]->n;
+    return off;
+  }
 };
 
 void wdf_server::launch(Slot &s) {
-  // pack: request r's feature f goes to column offset `off` of row f
-  int64_t off = 0;
-  for (auto &r : s.reqs) {
-    for (int f = 0; f < F; ++f)
-      std::memcpy(s.hx + (size_t)f * (size_t)max_rows + (size_t)off, r->x + (size_t)f * (size_t)r->ldx,
-                  (size_t)r->n * sizeof(float));
-    off += r->n;
-  }
-  s.rows = off;
-  const size_t pitch = (size_t)max_rows * sizeof(float);
-  hipError_t e = hipEventRecord(s.start, s.stream);
+  // pack: the copy threads split the features; request r's feature f goes to
+  // column offset off[r] of staging row f
+  const std::vector<int64_t> off = offsets(s);
+  const auto t0 = Clock::now();
+  const size_t ld = (size_t)batch_rows;
+  pool->run(copy_parts, [&](int p) {
+    const int f0 = (int)((int64_t)F * p / copy_parts), f1 = (int)((int64_t)F * (p + 1) / copy_parts);
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+      const Request &r = *s.reqs[i];
+      for (int f = f0; f < f1; ++f)
+        std::memcpy(s.hx + (size_t)f * ld + (size_t)off[i], r.x + (size_t)f * (size_t)r.ldx, (size_t)r.n * sizeof(float));
+    }
+  });
+  const double pm = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  s.rows = off.empty() ? 0 : off.back() + s.reqs.back()->n;
+  const size_t pitch = ld * sizeof(float);
+  hipError_t e = hipEventRecord(s.ev[0], s.stream);
   if (e == hipSuccess)
-    e = hipMemcpy2DAsync(s.dx, pitch, s.hx, pitch, (size_t)off * sizeof(float), (size_t)F,
-                                  hipMemcpyHostToDevice, s.stream);
-  int rc = e == hipSuccess ? WDF_OK : wdf::hip_error(e, "server: copy in");
-  if (rc == WDF_OK) rc = wdf_explain(bg, s.dx, off, max_rows, s.dphi, max_rows, s.stream);
-  if (rc == WDF_OK) {
-    e = hipMemcpy2DAsync(s.hphi, pitch, s.dphi, pitch, (size_t)off * sizeof(float), (size_t)F, hipMemcpyDeviceToHost,
+    e = hipMemcpy2DAsync(s.dx, pitch, s.hx, pitch, (size_t)s.rows * sizeof(float), (size_t)F, hipMemcpyHostToDevice,
                          s.stream);
+  if (e == hipSuccess) e = hipEventRecord(s.ev[1], s.stream);
+  int rc = e == hipSuccess ? WDF_OK : wdf::hip_error(e, "server: copy in");
+  if (rc == WDF_OK) rc = wdf_explain(bg, s.dx, s.rows, batch_rows, s.dphi, batch_rows, s.stream);
+  if (rc == WDF_OK) {
+    e = hipEventRecord(s.ev[2], s.stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(s.hphi, pitch, s.dphi, pitch, (size_t)s.rows * sizeof(float), (size_t)F,
+                           hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.ev[3], s.stream);
     if (e != hipSuccess) rc = wdf::hip_error(e, "server: copy out");
   }
-  if (rc == WDF_OK && (e = hipEventRecord(s.done, s.stream)) != hipSuccess) rc = wdf::hip_error(e, "server: event");
+  std::lock_guard<std::mutex> lock(mu);
+  pack_ms += pm;
   if (rc != WDF_OK) {
-    std::lock_guard<std::mutex> lock(mu);
     worker_error = rc;
     for (auto &r : s.reqs) {
       r->status = rc;
@@ -127,15 +223,27 @@ void wdf_server::launch(Slot &s) {
 }
 
 void wdf_server::drain(Slot &s) {
-  int64_t off = 0;
-  for (auto &r : s.reqs) {
-    for (int f = 0; f < F; ++f)
-      std::memcpy(r->phi_out + (size_t)f * (size_t)r->n, s.hphi + (size_t)f * (size_t)max_rows + (size_t)off,
-                  (size_t)r->n * sizeof(float));
-    off += r->n;
-  }
+  float t[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < 3; ++k) (void)hipEventElapsedTime(&t[k], s.ev[k], s.ev[k + 1]);
+  const std::vector<int64_t> off = offsets(s);
+  const auto t0 = Clock::now();
+  const size_t ld = (size_t)batch_rows;
+  pool->run(copy_parts, [&](int p) {
+    const int f0 = (int)((int64_t)F * p / copy_parts), f1 = (int)((int64_t)F * (p + 1) / copy_parts);
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+      const Request &r = *s.reqs[i];
+      for (int f = f0; f < f1; ++f)
+        std::memcpy(r.phi_out + (size_t)f * (size_t)r.n, s.hphi + (size_t)f * ld + (size_t)off[i],
+                    (size_t)r.n * sizeof(float));
+    }
+  });
   const auto now = Clock::now();
   std::lock_guard<std::mutex> lock(mu);
+  unpack_ms += std::chrono::duration<double, std::milli>(now - t0).count();
+  copy_in_ms += t[0];
+  explain_ms += t[1];
+  copy_out_ms += t[2];
+  busy_ms += (double)t[0] + (double)t[1] + (double)t[2];
   for (auto &r : s.reqs) {
     r->done = true;
     const double ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
@@ -145,6 +253,7 @@ void wdf_server::drain(Slot &s) {
       latency_ms[(size_t)(latency_next++ % kLatencyWindow)] = ms;
     ++completed;
   }
+  last_done = now;
   ++batches;
   rows += (uint64_t)s.rows;
   s.reqs.clear();
@@ -156,14 +265,14 @@ void wdf_server::run() {
   (void)hipSetDevice(device);
   for (;;) {
     // 1. fill free slots from the queue (FIFO; a batch takes the oldest
-    //    requests that fit in max_rows rows)
+    //    requests that fit in batch_rows rows), unless paused
     std::vector<Slot *> to_launch;
     {
       std::lock_guard<std::mutex> lock(mu);
       for (auto &s : slots) {
-        if (s.busy || queue.empty()) continue;
+        if (paused || s.busy || queue.empty()) continue;
         int64_t rows_in = 0;
-        while (!queue.empty() && rows_in + queue.front()->n <= max_rows) {
+        while (!queue.empty() && rows_in + queue.front()->n <= batch_rows) {
           rows_in += queue.front()->n;
           s.reqs.push_back(queue.front());
           queue.pop_front();
@@ -174,15 +283,8 @@ void wdf_server::run() {
     }
     for (Slot *s : to_launch) launch(*s);
     // 2. drain every finished slot
-    for (auto &s : slots) {
-      if (!s.busy || hipEventQuery(s.done) != hipSuccess) continue;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, s.start, s.done) == hipSuccess) {
-        std::lock_guard<std::mutex> lock(mu);
-        busy_ms += ms;
-      }
-      drain(s);
-    }
+    for (auto &s : slots)
+      if (s.busy && hipEventQuery(s.ev[3]) == hipSuccess) drain(s);
     // 3. wait for something to do
     Slot *oldest = nullptr;
     bool any_free = false;
@@ -192,32 +294,41 @@ void wdf_server::run() {
     }
     std::unique_lock<std::mutex> lock(mu);
     if (!oldest) {
-      cv_work.wait(lock, [&] { return stop || !queue.empty(); });
-      if (stop && queue.empty()) break;
-    } else if (!any_free) {
-      lock.unlock();
-      (void)hipEventSynchronize(oldest->done);
-    } else if (queue.empty()) {
-      // a batch is in flight and a slot is free: wake on a new request or
-      // shortly after, to collect the batch
-      cv_work.wait_for(lock, std::chrono::microseconds(100), [&] { return stop || !queue.empty(); });
+      cv_work.wait(lock, [&] { return stop || (!paused && !queue.empty()); });
+      if (stop && (queue.empty() || paused)) break;
+    } else if (!any_free || paused || queue.empty()) {
+      // a batch is in flight and nothing can be admitted: wait for the
+      // oldest batch, or shortly for a new request when a slot is free
+      if (!any_free || paused) {
+        lock.unlock();
+        (void)hipEventSynchronize(oldest->ev[3]);
+      } else {
+        cv_work.wait_for(lock, std::chrono::microseconds(50), [&] { return stop || !queue.empty(); });
+      }
     }
   }
 }
 
-extern "C" int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_rows, int queue_cap, int flags,
-                                 wdf_server **out) {
-  if (!bg || !out) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: NULL argument");
+extern "C" int wdf_server_create(const wdf_bg *bg, const wdf_server_config *cfg, wdf_server **out) {
+  if (!bg || !cfg || !out) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: NULL argument");
   *out = nullptr;
   if (bg->iv) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: serving explains Shapley/Banzhaf values");
-  if (max_rows < 1 || queue_cap < 1)
-    return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: max_rows and queue_cap must be >= 1");
+  const int64_t max_rows = cfg->max_rows;
+  const int64_t batch_rows = cfg->batch_rows > 0 ? cfg->batch_rows : std::max<int64_t>(max_rows, 65536);
+  if (max_rows < 1 || cfg->queue_cap < 1 || batch_rows < max_rows || batch_rows > (1 << 24) || cfg->copy_threads < 0 ||
+      cfg->copy_threads > 64)
+    return wdf::set_error(WDF_E_INVALID_ARG,
+                          "wdf_server_create: need max_rows >= 1, max_rows <= batch_rows <= 2^24, queue_cap >= 1, "
+                          "0 <= copy_threads <= 64");
+  const bool one = (cfg->flags & WDF_SERVE_ONE_PER_LAUNCH) != 0;
   const int F = bg->model->n_features;
-  const size_t per_slot = (size_t)4 * (size_t)F * (size_t)max_rows * sizeof(float);  // pinned + device, in + out
-  const size_t n_slots = std::min<size_t>(4, mem_budget / per_slot);
-  if (n_slots < 1)
+  // a plain one-request-per-launch server stages one request at a time
+  const int64_t slot_rows = one ? max_rows : batch_rows;
+  const size_t per_slot = (size_t)4 * (size_t)F * (size_t)slot_rows * sizeof(float);  // pinned + device, in + out
+  const size_t n_slots = one ? 1 : std::min<size_t>(4, cfg->mem_budget / per_slot);
+  if (n_slots < 1 || cfg->mem_budget < per_slot)
     return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_create: budget %zu bytes is below one batch slot (%zu bytes)",
-                          mem_budget, per_slot);
+                          cfg->mem_budget, per_slot);
   hipError_t e = hipSetDevice(bg->device);
   if (e != hipSuccess) return wdf::hip_error(e, "hipSetDevice");
   std::unique_ptr<wdf_server> S(new (std::nothrow) wdf_server());
@@ -226,23 +337,42 @@ extern "C" int wdf_server_create(const wdf_bg *bg, size_t mem_budget, int max_ro
   S->device = bg->device;
   S->F = F;
   S->max_rows = max_rows;
-  S->queue_cap = queue_cap;
-  S->one_per_launch = (flags & WDF_SERVE_ONE_PER_LAUNCH) != 0;
+  S->batch_rows = slot_rows;
+  S->queue_cap = cfg->queue_cap;
+  S->one_per_launch = one;
+  S->paused = (cfg->flags & WDF_SERVE_START_PAUSED) != 0;
+  const int threads = cfg->copy_threads > 0 ? cfg->copy_threads : 4;
+  S->copy_parts = std::min(threads, F);
+  S->pool.reset(new CopyPool(S->copy_parts));
   S->slots.resize(n_slots);
-  const size_t bytes = (size_t)F * (size_t)max_rows * sizeof(float);
+  const size_t bytes = (size_t)F * (size_t)slot_rows * sizeof(float);
   for (auto &s : S->slots) {
     if ((e = hipHostMalloc((void **)&s.hx, bytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void **)&s.hphi, bytes, hipHostMallocDefault)) != hipSuccess ||
         (e = hipMalloc((void **)&s.dx, bytes)) != hipSuccess || (e = hipMalloc((void **)&s.dphi, bytes)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreate(&s.start)) != hipSuccess || (e = hipEventCreate(&s.done)) != hipSuccess) {
+        (e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) {
       wdf_server_destroy(S.release());
       return wdf::set_error(WDF_E_OOM, "wdf_server_create: %s", hipGetErrorString(e));
     }
+    for (auto &ev : s.ev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) {
+        wdf_server_destroy(S.release());
+        return wdf::set_error(WDF_E_OOM, "wdf_server_create: %s", hipGetErrorString(e));
+      }
   }
   wdf_server *raw = S.release();
   raw->worker = std::thread([raw] { raw->run(); });
   *out = raw;
+  return WDF_OK;
+}
+
+extern "C" int wdf_server_pause(wdf_server *srv, int paused) {
+  if (!srv) return wdf::set_error(WDF_E_INVALID_ARG, "wdf_server_pause: NULL server");
+  {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->paused = paused != 0;
+  }
+  srv->cv_work.notify_all();
   return WDF_OK;
 }
 
@@ -264,6 +394,7 @@ extern "C" int wdf_server_submit(wdf_server *srv, const float *X_host, int64_t n
   }
   r->ticket = srv->next_ticket++;
   r->t_submit = Clock::now();
+  if (!srv->any_submit) srv->first_submit = r->t_submit, srv->any_submit = true;
   srv->pending[r->ticket] = r;
   srv->queue.push_back(r);
   ++srv->submitted;
@@ -300,6 +431,16 @@ extern "C" int wdf_server_stats(wdf_server *srv, wdf_stats *out) {
     out->batches = srv->batches;
     out->rows = srv->rows;
     out->busy_ms = srv->busy_ms;
+    out->copy_in_ms = srv->copy_in_ms;
+    out->explain_ms = srv->explain_ms;
+    out->copy_out_ms = srv->copy_out_ms;
+    out->pack_ms = srv->pack_ms;
+    out->unpack_ms = srv->unpack_ms;
+    out->active_ms = (srv->any_submit && srv->completed)
+                         ? std::chrono::duration<double, std::milli>(srv->last_done - srv->first_submit).count()
+                         : 0.0;
+    out->slots = (int)srv->slots.size();
+    out->batch_rows = srv->batch_rows;
     lat = srv->latency_ms;
   }
   out->p50_ms = out->p99_ms = out->mean_ms = out->max_ms = 0.0;
@@ -325,14 +466,15 @@ extern "C" void wdf_server_destroy(wdf_server *srv) {
   {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->stop = true;
+    srv->paused = false;  // queued requests are explained before the worker stops
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
   (void)hipSetDevice(srv->device);
   for (auto &s : srv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
-    if (s.start) (void)hipEventDestroy(s.start);
-    if (s.done) (void)hipEventDestroy(s.done);
+    for (auto &ev : s.ev)
+      if (ev) (void)hipEventDestroy(ev);
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.dx) (void)hipFree(s.dx);
     if (s.dphi) (void)hipFree(s.dphi);

@@ -41,6 +41,7 @@ KERNEL_PAIRS = 16          # flag: one table per sibling pair in the specialised
 
 MAX_DEPTH = 8
 SERVE_ONE_PER_LAUNCH = 1
+SERVE_START_PAUSED = 2
 
 
 class WdfError(RuntimeError):
@@ -63,8 +64,18 @@ class Stats(C.Structure):
         ("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
         ("batches", C.c_uint64), ("rows", C.c_uint64),
         ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
-        ("busy_ms", C.c_double),
+        ("busy_ms", C.c_double), ("copy_in_ms", C.c_double), ("explain_ms", C.c_double),
+        ("copy_out_ms", C.c_double), ("pack_ms", C.c_double), ("unpack_ms", C.c_double),
+        ("active_ms", C.c_double), ("slots", C.c_int), ("batch_rows", C.c_int64),
     ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("mem_budget", C.c_size_t), ("max_rows", C.c_int), ("batch_rows", C.c_int),
+                ("queue_cap", C.c_int), ("flags", C.c_int), ("copy_threads", C.c_int)]
 
 
 _lib = None
@@ -104,7 +115,7 @@ EXPORTS = [
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables", "wdf_debug_time_contraction",
     "wdf_debug_specialised_source", "wdf_debug_iv_source", "wdf_debug_coef_matrix", "wdf_model_autotune",
     "wdf_model_set_tuning", "wdf_debug_hist_launch", "wdf_server_create",
-    "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
+    "wdf_server_pause", "wdf_server_submit", "wdf_server_wait", "wdf_server_stats", "wdf_server_destroy",
 ]
 
 
@@ -154,7 +165,8 @@ def lib():
         L.wdf_model_set_tuning.argtypes = [P, C.POINTER(Tuning)]
         L.wdf_debug_hist_launch.argtypes = [P, I64, P, P, I64]
         L.wdf_debug_hist_launch.restype = I64
-        L.wdf_server_create.argtypes = [P, C.c_size_t, I, I, I, C.POINTER(P)]
+        L.wdf_server_create.argtypes = [P, C.POINTER(ServerConfig), C.POINTER(P)]
+        L.wdf_server_pause.argtypes = [P, I]
         L.wdf_server_submit.argtypes = [P, P, I64, I64, P, C.POINTER(C.c_uint64)]
         L.wdf_server_wait.argtypes = [P, C.c_uint64, I]
         L.wdf_server_stats.argtypes = [P, C.POINTER(Stats)]
@@ -533,15 +545,21 @@ class Server:
     """Continuous-batching explain server over a resident background summary."""
 
     def __init__(self, bg: Background, mem_budget: int, max_rows: int = 4096, queue_cap: int = 1 << 16,
-                 one_per_launch: bool = False):
+                 one_per_launch: bool = False, batch_rows: int = 0, copy_threads: int = 0, paused: bool = False):
         self.bg = bg
         self.n_features = bg.model.n_features
         self._inflight = {}
+        cfg = ServerConfig(mem_budget, max_rows, batch_rows, queue_cap,
+                           (SERVE_ONE_PER_LAUNCH if one_per_launch else 0) | (SERVE_START_PAUSED if paused else 0),
+                           copy_threads)
         h = C.c_void_p()
-        _check(lib().wdf_server_create(bg.h, mem_budget, max_rows, queue_cap, SERVE_ONE_PER_LAUNCH if one_per_launch else 0,
-                                       C.byref(h)))
+        _check(lib().wdf_server_create(bg.h, C.byref(cfg), C.byref(h)))
         self.h = h
         _track(self)
+
+    def pause(self, paused: bool = True):
+        """Stop (or resume) admitting queued requests into batches."""
+        _check(lib().wdf_server_pause(self.h, 1 if paused else 0))
 
     def submit(self, X: np.ndarray, phi: np.ndarray) -> int:
         """X: float32 [F, n] host array (C order); phi: float32 [F, n] C-order host array that
