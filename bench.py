@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,6 +29,13 @@ from paper_2511_09376_amd import synth  # noqa: E402
 METRIC = "Background-SHAP rows/s (100 trees d6, 127 feat) + served p50/p99 latency"
 VALU_PEAK_OPS = 256 * 64 * 2.4e9   # 32-bit lane operations per second (non-packed)
 HBM_PEAK = 8.0e12                  # bytes per second
+MFMA_F64_PEAK = 78.6e12            # dense FP64 matrix flops per second
+# The paper's own run of this method at this shape (Section 10, KDD-Cup-99):
+# 2,984,154 consumers x 4,898,431 background rows x 127 features, XGBoost
+# regressor with 100 trees of depth 6, on Colab hardware.
+PAPER_CONTEXT = {"cpu_s": 162.0, "gpu_s": 16.0, "cpu": "Colab CPU runtime", "gpu": "A100 (Colab), CuPy",
+                 "consumers": 2984154, "background": 4898431, "features": 127, "trees": 100, "depth": 6,
+                 "cpu_rows_per_s": 2984154 / 162.0, "gpu_rows_per_s": 2984154 / 16.0}
 
 DESCRIPTIONS = {
     "paper": "paper-scale shape: 100 complete depth-6 trees, 127 features (normal/log-normal/binary/count mix, 5% NaN), 3M consumer rows x 5M background rows",
@@ -83,37 +91,103 @@ def measured_traffic(wdf, ens, workload, gather):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(ens, X_rows, B, seconds_hint=20.0):
-    """The FP64 oracle (depth-first walk form), unchanged, on a bounded sample:
-    one consumer row per host core against a prefix of the background sized to
-    take about `seconds_hint` seconds.  The oracle's work is linear in the
-    background size, so the measured rate is scaled to the full background."""
+def cpu_model_name() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    """Threads for the CPU oracle: the CPUs this process may run on, at most
+    16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(ens, X, B, rows, threads, kind):
+    """The FP64 oracle (depth-first walk form), unchanged, on `rows` (seeded
+    consumer rows) against the full background, on `threads` host threads; no
+    scaling: the rate is rows over the measured wall time.  Returns the
+    baseline record and the oracle's phi of those rows."""
     import oracle
-    cores = max(1, min(16, os.cpu_count() or 1))
     om = oracle.Model(ens)
+    Xs = np.ascontiguousarray(X[:, rows])
     m = B.shape[1]
-    probe_m = min(m, 20_000)
     t0 = time.perf_counter()
-    oracle.bg_walk(om, np.ascontiguousarray(X_rows[:, :1]), np.ascontiguousarray(B[:, :probe_m]), threads=1)
-    per_bg_row = (time.perf_counter() - t0) / probe_m
-    m_s = int(max(1, min(m, seconds_hint / max(per_bg_row, 1e-12))))
-    rows = min(cores, X_rows.shape[1])
-    Xs = np.ascontiguousarray(X_rows[:, :rows])
-    Bs = np.ascontiguousarray(B[:, :m_s])
-    t0 = time.perf_counter()
-    oracle.bg_walk(om, Xs, Bs, threads=rows)
+    ref = oracle.bg_walk(om, Xs, B, kind=kind, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": rows / dt * (m_s / m), "unit": "rows/s", "cores": rows, "kind": "oracle",
-            "sample": f"{rows} consumer rows (one per thread) x the first {m_s} of {m} background rows in {dt:.1f} s; "
-                      f"rate scaled by {m_s}/{m} to the full background (the oracle's work is linear in it)"}
+    rec = {"value": len(rows) / dt, "unit": "rows/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(rows)} seeded consumer rows x all {m} background rows, {threads} threads, "
+                     f"{dt:.1f} s wall (no scaling)",
+           "seconds": dt, "rows": len(rows), "nproc": os.cpu_count(), "cpu_model": cpu_model_name()}
+    return rec, ref
 
 
-def serve_bench(wdf, ctx, loads=(0.5, 0.8), n_requests=10_000, max_rows=4096):
+def run_error(got, ref, rows):
+    """phi of the timed run on the oracle's rows: the maximum absolute error
+    and the row-scaled error (per row, max_i |phi - ref| over max_i |ref|)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    diff = np.abs(got - ref)
+    scale = np.maximum(np.abs(ref).max(axis=0), 1e-30)
+    row_scaled = float((diff.max(axis=0) / scale).max())
+    return {"max_abs": float(diff.max()), "row_scaled": row_scaled, "rows": int(len(rows)),
+            "tolerance": 1e-5, "within_tolerance": bool(row_scaled <= 1e-5),
+            "against": "FP64 oracle walk with the full background"}
+
+
+def pcie_rates(F, rows=1 << 18, reps=5):
+    """Pinned host <-> device copy rates (GB/s) of a [F][rows] float32 block,
+    each direction alone and both at once on two streams, and what they allow
+    a server that copies every row in (4 F bytes) and out (4 F bytes)."""
+    import torch
+    n = F * rows
+    h_in = torch.empty(n, dtype=torch.float32, pin_memory=True)
+    h_out = torch.empty(n, dtype=torch.float32, pin_memory=True)
+    d_in = torch.empty(n, dtype=torch.float32, device="cuda")
+    d_out = torch.zeros(n, dtype=torch.float32, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def both():
+        with torch.cuda.stream(s1):
+            d_in.copy_(h_in, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h_out.copy_(d_out, non_blocking=True)
+
+    bytes_ = 4 * n
+    h2d = bytes_ / timed(lambda: d_in.copy_(h_in, non_blocking=True)) / 1e9
+    d2h = bytes_ / timed(lambda: h_out.copy_(d_out, non_blocking=True)) / 1e9
+    duplex = 2 * bytes_ / timed(both) / 1e9
+    return {"h2d_gbs": h2d, "d2h_gbs": d2h, "both_directions_gbs": duplex,
+            "rows_per_s_ceiling": duplex * 1e9 / (2 * 4 * F),
+            "note": f"pinned copies of {bytes_ >> 20} MiB; a served row moves 4 F bytes in and 4 F bytes out"}
+
+
+def serve_bench(wdf, ctx, loads=(0.5, 0.8), n_requests=10_000, max_rows=4096, batch_rows=1 << 16, copy_threads=8):
     """Serving: the 100-tree depth-6 model and a 100k-row background resident on
     the device; requests of log-uniform size in [1, 4096] rows arrive as a
     Poisson process at a fixed fraction of the server's saturated throughput.
-    Continuous batching is compared with one request per launch at the same
-    offered load.  Latency is submit -> phi on the host."""
+    Continuous batching (batches of up to batch_rows rows in up to four slots,
+    packed and unpacked by copy threads) is compared with the plain form, one
+    request per launch, at the same offered load.  Latency is submit -> phi on
+    the host."""
     import torch
     w = synth.WORKLOADS["serve"]
     ens = w.ensemble()
@@ -127,10 +201,11 @@ def serve_bench(wdf, ctx, loads=(0.5, 0.8), n_requests=10_000, max_rows=4096):
     reqs = [np.ascontiguousarray(pool[:, s:s + n]) for s, n in zip(starts, sizes)]
     outs = [np.empty_like(x) for x in reqs]
     F = model.n_features
-    budget = 4 * (4 * F * max_rows * 4)
+    budget = 4 * (4 * F * batch_rows * 4)
 
     def run(one_per_launch, rate_rows):
-        srv = wdf.Server(bg, budget, max_rows, queue_cap=n_requests, one_per_launch=one_per_launch)
+        srv = wdf.Server(bg, budget, max_rows, queue_cap=n_requests, one_per_launch=one_per_launch,
+                         batch_rows=batch_rows, copy_threads=copy_threads)
         gaps = np.random.default_rng(7).exponential(1.0, n_requests) if rate_rows else np.zeros(n_requests)
         mean_size = float(sizes.mean())
         if rate_rows:
@@ -143,19 +218,25 @@ def serve_bench(wdf, ctx, loads=(0.5, 0.8), n_requests=10_000, max_rows=4096):
             while time.perf_counter() < target:
                 pass
             tickets.append(srv.submit(reqs[i], outs[i]))
+        t_sub = time.perf_counter() - t0
         for t in tickets:
             srv.wait(t)
         dt = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
         return {"rows_per_s": float(sizes.sum()) / dt, "requests": int(st.completed), "batches": int(st.batches),
-                "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "max_ms": st.max_ms}
+                "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "max_ms": st.max_ms,
+                "wall_ms": dt * 1e3, "submit_ms": t_sub * 1e3, "slots": int(st.slots),
+                "batch_rows": int(st.batch_rows), "device_busy_ms": st.busy_ms, "copy_in_ms": st.copy_in_ms,
+                "explain_ms": st.explain_ms, "copy_out_ms": st.copy_out_ms, "pack_ms": st.pack_ms,
+                "unpack_ms": st.unpack_ms}
 
     run(False, 0)                                  # warm-up
     cap = run(False, 0)                            # saturated throughput
     out = {"workload": "100 complete depth-6 trees, 127 features, 100k background rows resident; "
                        f"{n_requests} Poisson requests, sizes log-uniform in [1, {max_rows}] (mean {sizes.mean():.0f} rows)",
-           "saturated_rows_per_s": cap["rows_per_s"], "loads": []}
+           "saturated_rows_per_s": cap["rows_per_s"], "saturated": cap, "copy_threads": copy_threads,
+           "pcie": pcie_rates(F), "loads": []}
     for load in loads:
         rate = load * cap["rows_per_s"]
         out["loads"].append({"offered_fraction": load, "offered_rows_per_s": rate,
@@ -173,7 +254,9 @@ def main():
     ap.add_argument("--workload", default="paper", choices=list(DESCRIPTIONS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic", "specialised", "pairs"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-rows", type=int, default=16,
+                    help="seeded consumer rows the CPU oracle explains against the full background (also the rows "
+                         "on which the timed phi is checked)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--values", default="shapley", choices=["shapley", "banzhaf", "shapley_iv", "banzhaf_iv"],
@@ -318,6 +401,22 @@ def main():
                     "kernel": f"wdf_explain_{gather}" if gather else "k_explain_generic", "kernel_ms": explain_ms,
                     "ops_per_row": ops_row}
     base = bg.base_value
+    rows_check = np.sort(np.random.default_rng(2511).choice(n, min(n, args.cpu_rows), replace=False))
+    phi_rows = phi[:, torch.from_numpy(rows_check).cuda()].cpu().numpy() if not iv else None
+    hbm = None
+    mfma = None
+    if not iv:
+        alg = 2 * 4 * ens.n_features * n          # X read and phi written, once each
+        hbm = {"kernel": roofline["kernel"], "algorithmic_bytes": alg, "algorithmic_gbs": alg / (explain_ms * 1e6),
+               "measured_bytes": roofline["traffic"],
+               "measured_gbs": (roofline["traffic"] / (explain_ms * 1e6)) if roofline["traffic"] else None,
+               "peak_gbs": HBM_PEAK / 1e9}
+        hbm["measured_frac"] = hbm["measured_gbs"] / hbm["peak_gbs"] if hbm["measured_gbs"] else None
+        if not args.pathdep:
+            c_ms, c_flops = bg.time_contraction(20, stream)
+            mfma = {"kernel": "k_gemm_f64 (v_mfma_f64_16x16x4f64)", "ms_per_contraction": c_ms, "flops": c_flops,
+                    "tflops": c_flops / (c_ms * 1e9), "peak_tflops": MFMA_F64_PEAK / 1e12,
+                    "util": c_flops / (c_ms * 1e-3) / MFMA_F64_PEAK}
     out = {"metric": METRIC, "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -328,7 +427,8 @@ def main():
                       "values": args.values, "background": "path-dependent (covers)" if args.pathdep else "rows"},
            "roofline": roofline, "base_value": base, "tuning": tuning,
            "explain_rows_per_s": n / (explain_ms * 1e-3),
-           "background_ms": ms_step - explain_ms}
+           "background_ms": ms_step - explain_ms, "hbm": hbm, "mfma": mfma,
+           "paper_context": dict(PAPER_CONTEXT, this_run_s_per_3m_rows=3e6 / value)}
     if summary_once_ms is not None:
         out["pathdep_summary_once_ms"] = summary_once_ms
     if not args.no_serve:
@@ -336,9 +436,15 @@ def main():
         out["serving"] = serve_bench(wdf, ctx)
         sv = out["serving"]["loads"][0]["continuous_batching"]
         out["served_p50_ms"], out["served_p99_ms"] = sv["p50_ms"], sv["p99_ms"]
-    if not args.no_cpu_baseline and not args.pathdep and args.values == "shapley":  # the headline method only
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(ens, X[:, :64], B, args.cpu_seconds)
+    if not args.no_cpu_baseline and not args.pathdep and not iv:
+        threads = host_threads()
+        print(f"[bench] CPU oracle: {rows_check.size} rows x {B.shape[1]} background rows on {threads} threads",
+              file=sys.stderr, flush=True)
+        kind = 0 if args.values == "shapley" else 1
+        out["cpu_baseline"], ref = cpu_baseline(ens, X, B, rows_check, threads, kind)
+        out["error"] = run_error(phi_rows, ref, rows_check)
+        print(f"[bench] oracle done in {out['cpu_baseline']['seconds']:.1f} s; row-scaled error "
+              f"{out['error']['row_scaled']:.3e}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -54,14 +54,36 @@ def test_more_than_one_gpu_is_refused():
 
 def test_cpu_baseline_leg(bench):
     """The oracle leg of the bench line on a tiny workload: the documented keys,
-    a positive rate, the thread count it used, and a bounded sample."""
+    a positive rate from the measured wall time (no scaling), the thread count
+    and host it used, every background row, and the oracle's phi of exactly
+    the sampled rows."""
+    import oracle
     w = synth.WORKLOADS["small"]
     ens, X, B = w.ensemble(), w.consumers(), w.background()
-    out = bench.cpu_baseline(ens, X, B, seconds_hint=0.2)
-    assert set(out) == {"value", "unit", "cores", "kind", "sample"}
+    rows = [3, 17, 99]
+    out, ref = bench.cpu_baseline(ens, X, B, rows, threads=2, kind=0)
+    assert {"value", "unit", "cores", "kind", "sample", "seconds", "rows", "nproc", "cpu_model"} <= set(out)
     assert out["kind"] == "oracle" and out["unit"] == "rows/s" and out["value"] > 0
-    assert 1 <= out["cores"] <= min(16, os.cpu_count() or 1, X.shape[1])
-    assert "background rows" in out["sample"]
+    assert out["cores"] == 2 and out["rows"] == 3
+    assert abs(out["value"] - 3 / out["seconds"]) <= 1e-9 * out["value"]
+    assert f"all {B.shape[1]} background rows" in out["sample"] and "no scaling" in out["sample"]
+    assert out["cpu_model"] and out["nproc"] >= 1
+    assert ref.shape == (ens.n_features, 3)
+    assert (ref == oracle.bg_walk(oracle.Model(ens), X[:, rows], B, threads=1)).all()
+    assert 1 <= bench.host_threads() <= 16
+
+
+def test_run_error(bench):
+    """The per-run error record: maximum absolute and row-scaled error
+    against the oracle's rows, and the 1e-5 gate."""
+    import numpy as np
+    ref = np.array([[1.0, -2.0], [0.5, 0.0]])
+    got = ref + np.array([[1e-6, 0.0], [0.0, 4e-5]])
+    e = bench.run_error(got, ref, [5, 6])
+    assert e["rows"] == 2 and abs(e["max_abs"] - 4e-5) < 1e-15
+    assert abs(e["row_scaled"] - 2e-5) < 1e-15            # row 2: 4e-5 / 2.0
+    assert e["within_tolerance"] is False
+    assert bench.run_error(ref, ref, [5, 6])["within_tolerance"] is True
 
 
 def test_traffic_summary_matches_the_current_explain_kernel(bench):
