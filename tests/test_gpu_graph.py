@@ -110,3 +110,23 @@ def test_refresh_errors(wdf, ctx, mid_data):
         pd.refresh(Bs[0])
     with pytest.raises(wdf.WdfError):
         wdf.Graph(bg)                          # nothing to record
+
+
+@pytest.mark.parametrize("kname", ["auto", "generic"])
+def test_base_value_before_the_first_replay(wdf, ctx, mid_data, kname):
+    """A graph that refreshes the summary reads the base value (Appendix B.1
+    efficiency reference) from the device from its creation on: before the
+    first replay it is the load's value, after a replay the new background's."""
+    ens, Bs, X = mid_data
+    model = wdf.Model(ctx, ens, _kernel(wdf, kname))
+    bg = wdf.Background(model, Bs[0])
+    base0 = bg.base_value
+    g = wdf.Graph(bg, B=Bs[1])
+    assert bg.base_value == base0
+    g.launch()
+    torch.cuda.synchronize()
+    ref = wdf.Background(model, Bs[1])
+    assert bg.base_value == ref.base_value != base0
+    g.close()
+    ref.close()
+    bg.close()

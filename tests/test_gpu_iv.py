@@ -76,16 +76,22 @@ def test_edge_iv(wdf, ctx, n):
     assert _iv_error(got, ref) <= 1e-5
 
 
-def test_mid_iv_sampled_rows(wdf, ctx):
+@pytest.mark.parametrize("kind", ["shapley", "banzhaf"])
+def test_mid_iv_sampled_rows(wdf, ctx, kind):
+    """Shapley (Table table_shap_iv) and Banzhaf (Formula
+    banzhaf_simplified_formula_interactions) interaction values of the
+    100-tree depth-6 model: sampled rows against the oracle's walk."""
     w = synth.WORKLOADS["mid"]
     ens = w.ensemble()
     B = w.background(4099)
     X = w.consumers(70)
     model = wdf.Model(ctx, ens, wdf.KERNEL_AUTO)
-    bg = wdf.Background(model, _cuda(B), values=wdf.SHAPLEY_IV)
+    values = wdf.SHAPLEY_IV if kind == "shapley" else wdf.BANZHAF_IV
+    bg = wdf.Background(model, _cuda(B), values=values)
     got = bg.explain_iv(_cuda(X)).cpu().numpy()
     rows = [0, 33, 69]
-    ref = oracle.bg_iv_walk(oracle.Model(ens), np.ascontiguousarray(X[:, rows]), B, threads=8)
+    okind = oracle.SHAPLEY if kind == "shapley" else oracle.BANZHAF
+    ref = oracle.bg_iv_walk(oracle.Model(ens), np.ascontiguousarray(X[:, rows]), B, kind=okind, threads=8)
     assert _iv_error(got[:, :, rows], ref) <= 1e-5
     assert np.isfinite(got).all()
 

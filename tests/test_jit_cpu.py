@@ -134,7 +134,7 @@ def test_iv_source_matches_the_layout(wdf, which):
             assert v == f"a{j}"
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("values", ["shapley", "banzhaf", "shapley_iv", "banzhaf_iv"])
 def test_host_coefficient_matrices_match_the_oracle(wdf, d, values):
     """The library's host-built matrices against the oracle: every pattern pair
