@@ -218,6 +218,24 @@ int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, flo
  * row; at least 1).  Errors: INVALID_ARG (NULL summary, n < 0). */
 int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * interaction values as wdf_explain_iv, same arguments and layout, with the
+ * rows' patterns kept in the library's own scratch array instead of a caller
+ * workspace.  The array is a file-scope device array of
+ * WDF_NOALLOC_SCRATCH_BYTES bytes that every device the library runs on holds
+ * until the process ends; the call allocates nothing and calls no allocating
+ * routine.  n rows need wdf_explain_iv_workspace(bg, n) bytes of it (one per
+ * group and row): larger calls fail with INVALID_ARG and the row limit in
+ * wdf_last_error().  All calls on one device share its array, which keeps the
+ * last call's patterns (every byte read is written first, so nothing needs
+ * clearing): calls that overlap on one device (different streams, or before
+ * the previous call's work has run) race and give wrong values; order them on
+ * one stream.  Errors: as wdf_explain_iv, and INVALID_ARG above the limit. */
+#define WDF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int wdf_explain_iv_noalloc(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
+                           void *hip_stream);
+
 /* mean_b f(b) in double precision (Appendix B.1 efficiency: sum_i phi_i(c) =
  * f(c) - base).  For a path-dependent summary: the cover-weighted mean.  After
  * a refresh (below) the value is read from the device: synchronise the

@@ -112,6 +112,9 @@ extern "C" int wdf_create(int device, wdf_ctx **out) {
   if (!c) return set_error(WDF_E_OOM, "wdf_create: out of host memory");
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
+  // the device address of the scratch array of the no-alloc entry points,
+  // resolved once per context with its device current
+  HIP_TRY(scratch_address(&c->scratch));
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   *out = c.release();
   return WDF_OK;
@@ -985,6 +988,22 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
                             M->d_iv_items.as<int2>(), bg->d_tab.as<float>(), X, n, ldx, (uint8_t *)workspace, iv, ldiv,
                             M->n_features, s));
   return WDF_OK;
+}
+
+extern "C" int wdf_explain_iv_noalloc(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv,
+                                      int64_t ldiv, void *hip_stream) {
+  if (!bg) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv_noalloc: NULL summary");
+  const int64_t need = wdf_explain_iv_workspace(bg, n);
+  if (need < 0) return (int)need;
+  if (need > (int64_t)WDF_NOALLOC_SCRATCH_BYTES)
+    return set_error(WDF_E_INVALID_ARG,
+                     "wdf_explain_iv_noalloc: %lld rows need %lld bytes of pattern scratch, above the library's "
+                     "%lld (explain at most %lld rows per call, or pass a workspace to wdf_explain_iv)",
+                     (long long)n, (long long)need, (long long)WDF_NOALLOC_SCRATCH_BYTES,
+                     (long long)(WDF_NOALLOC_SCRATCH_BYTES / std::max<int64_t>(need / std::max<int64_t>(n, 1), 1)));
+  // the pattern kernel writes every byte the interaction kernels read, so
+  // the scratch needs no clearing between calls
+  return wdf_explain_iv(bg, X, n, ldx, iv, ldiv, bg->model->ctx->scratch, WDF_NOALLOC_SCRATCH_BYTES, hip_stream);
 }
 
 extern "C" int wdf_debug_time_contraction(const wdf_bg *bg, int reps, void *hip_stream, double *flops, float *ms) {

@@ -89,6 +89,7 @@ struct wdf_ctx {
   int device = 0;
   int n_cu = 0;
   hipStream_t stream = nullptr;
+  void *scratch = nullptr;  // this device's address of the no-alloc scratch array
   std::mutex jit_mu;
   std::map<std::string, std::shared_ptr<wdf::JitPart>> jit_cache;  // by generated source
 };

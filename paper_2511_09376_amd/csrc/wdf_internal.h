@@ -38,5 +38,8 @@ hipError_t launch_explain_iv(const Group *groups, const PathNode *path, int64_t 
                              float *out, int64_t ldo, int F, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_xtab(const XUnit *units, int64_t n_units, const float *tab, float *xtab, hipStream_t s);
+// device address, on the current device, of the library's scratch array
+// (WDF_NOALLOC_SCRATCH_BYTES bytes) used by the entry points that allocate nothing
+hipError_t scratch_address(void **out);
 
 }  // namespace wdf

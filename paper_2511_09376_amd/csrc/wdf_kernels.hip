@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wdf.h"
 #include "wdf_dev.h"
 #include "wdf_internal.h"
 
@@ -681,6 +682,15 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
+
+// Scratch of the entry points that allocate nothing (wdf_explain_iv_noalloc):
+// one array per device, each device that loads the library holding its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: host code passes the address that
+// scratch_address() returns on the current device, never the name itself.
+static __device__ __align__(256) uint8_t scratch[WDF_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_address(void **out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
 
 hipError_t launch_xtab(const XUnit *units, int64_t n_units, const float *tab, float *xtab, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;

@@ -42,6 +42,7 @@ KERNEL_PAIRS = 16          # flag: one table per sibling pair in the specialised
 MAX_DEPTH = 8
 SERVE_ONE_PER_LAUNCH = 1
 SERVE_START_PAUSED = 2
+NOALLOC_SCRATCH_BYTES = 32 << 20   # the library's scratch array (wdf_explain_iv_noalloc)
 
 
 class WdfError(RuntimeError):
@@ -111,7 +112,7 @@ class Tuning(C.Structure):
 EXPORTS = [
     "wdf_last_error", "wdf_create", "wdf_destroy", "wdf_model_load", "wdf_model_destroy", "wdf_model_groups",
     "wdf_model_specialised", "wdf_bg_specialised", "wdf_background_load", "wdf_pathdep_load", "wdf_bg_destroy", "wdf_explain",
-    "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
+    "wdf_base_value", "wdf_explain_iv", "wdf_explain_iv_workspace", "wdf_explain_iv_noalloc", "wdf_background_refresh", "wdf_graph_create", "wdf_graph_launch", "wdf_graph_destroy",
     "wdf_debug_patterns", "wdf_debug_histograms", "wdf_debug_tables", "wdf_debug_time_contraction",
     "wdf_debug_specialised_source", "wdf_debug_iv_source", "wdf_debug_coef_matrix", "wdf_model_autotune",
     "wdf_model_set_tuning", "wdf_debug_hist_launch", "wdf_server_create",
@@ -143,6 +144,7 @@ def lib():
         L.wdf_explain.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_base_value.argtypes = [P, C.POINTER(C.c_double)]
         L.wdf_explain_iv.argtypes = [P, P, I64, I64, P, I64, P, C.c_size_t, P]
+        L.wdf_explain_iv_noalloc.argtypes = [P, P, I64, I64, P, I64, P]
         L.wdf_explain_iv_workspace.argtypes = [P, I64]
         L.wdf_explain_iv_workspace.restype = I64
         L.wdf_background_refresh.argtypes = [P, P, I64, P]
@@ -453,6 +455,28 @@ class Background:
             _check(lib().wdf_explain_iv(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()), ldo,
                                         C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                         _stream_handle(stream, dev)))
+        return out
+
+    def explain_iv_noalloc(self, X, out, stream=None):
+        """explain_iv with the patterns in the library's own scratch array
+        (wdf_explain_iv_noalloc): allocates nothing, so `out` [F, F, n] must
+        be given.  At most NOALLOC_SCRATCH_BYTES // groups rows per call;
+        calls on one device must not overlap."""
+        F = self.model.n_features
+        X = _colmajor_tensor(X, F, "X")
+        dev = self.model.ctx.device
+        _on_device(X, dev, "X")
+        _on_device(out, dev, "out")
+        n = X.shape[1]
+        import torch
+        if out.shape != (F, F, n) or out.dtype != torch.float32 or (n > 1 and out.stride(2) != 1) or \
+                out.stride(1) != out.stride(0) // F:
+            raise ValueError("out must be float32 [F, F, n] with rows contiguous")
+        ldx = X.stride(0) if n else 0
+        ldo = out.stride(1) if n else 0
+        with torch.cuda.device(dev):
+            _check(lib().wdf_explain_iv_noalloc(self.h, C.c_void_p(X.data_ptr()), n, ldx, C.c_void_p(out.data_ptr()),
+                                                ldo, _stream_handle(stream, dev)))
         return out
 
     def iv_workspace_bytes(self, n: int) -> int:
