@@ -35,9 +35,11 @@ struct Group {
 // are indexed by raw splits (bit 1: the row went left), not by whether the row
 // follows the path; `mask` holds the path's right turns, so the pattern of a
 // raw index r is r ^ mask.  Layout: E = 2^(depth + quad) entries of nv values,
-// stored as ceil(nv / 4) float4 planes [plane][entry], value v in component
+// stored as ceil(nv / 4) float4 planes [plane][slot], value v in component
 // v % 4 of plane v / 4 (unused components 0), so that one 16-byte LDS read
-// returns four values of an entry.
+// returns four values of an entry; entry I sits at slot I ^ (I >> 3) ^ (I >> 6)
+// of each plane, so that entries sharing their low three bits (one group of
+// LDS banks) are spread over all eight groups.
 struct XUnit {
   int64_t src_l;   // table offset of the (left) group
   int64_t src_r;   // table offset of the right pair group of a quad, -1 otherwise

@@ -243,10 +243,13 @@ typedef long long i64;
 // Node test on a threshold rank: t = rank - (j + 1) is negative exactly when
 // rank <= j, i.e. when the row goes left (TU: rank unsigned, so a NaN goes
 // right; TS: rank sign-extended, so a NaN goes left).  The caller shifts t's
-// sign bit into the pattern with alignbit: P' = 2 P + split.  The constant is
-// moved into an SGPR inside the asm, so it is not a loop-invariant register.
-#define TU(t, w, sel, j1) do { u32 s_; asm("s_mov_b32 %1, " #j1 "\n\tv_sub_u32_sdwa %0, %2, %1 src0_sel:" sel " src1_sel:DWORD" : "=v"(t), "=&s"(s_) : "v"(w)); } while (0)
-#define TS(t, w, sel, j1) do { u32 s_; asm("s_mov_b32 %1, " #j1 "\n\tv_sub_u32_sdwa %0, sext(%2), %1 src0_sel:" sel " src1_sel:DWORD" : "=v"(t), "=&s"(s_) : "v"(w)); } while (0)
+// sign bit into the pattern with alignbit: P' = 2 P + split.  j + 1 <= 64 is
+// an inline constant of the instruction (TU/TS); larger ones come in an SGPR
+// (TUX/TSX).  Tests share no register, so independent ones interleave.
+#define TU(t, w, sel, j1) asm("v_sub_u32_sdwa %0, %1, " #j1 " src0_sel:" sel " src1_sel:DWORD" : "=v"(t) : "v"(w))
+#define TS(t, w, sel, j1) asm("v_sub_u32_sdwa %0, sext(%1), " #j1 " src0_sel:" sel " src1_sel:DWORD" : "=v"(t) : "v"(w))
+#define TUX(t, w, sel, j1) asm("v_sub_u32_sdwa %0, %1, %2 src0_sel:" sel " src1_sel:DWORD" : "=v"(t) : "v"(w), "s"(j1))
+#define TSX(t, w, sel, j1) asm("v_sub_u32_sdwa %0, sext(%1), %2 src0_sel:" sel " src1_sel:DWORD" : "=v"(t) : "v"(w), "s"(j1))
 )";
 
 // the explain kernel is named by its gather, so that profiles tell the variants apart
@@ -314,16 +317,42 @@ struct Gen {
 
   void test(int64_t nd, const std::string &pout, const std::string &pin) {
     const int f = M->feature[(size_t)nd];
-    o << "u32 " << pout << "; { u32 t_; " << (M->default_left[(size_t)nd] ? "TS(" : "TU(") << "t_, w"
-      << f / M->jp.per_word << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] + 1 << "); " << pout
-      << " = __builtin_amdgcn_alignbit(" << pin << ", t_, 31); }\n";
+    const int j1 = M->jp.rank[(size_t)nd] + 1;
+    const char *mac = M->default_left[(size_t)nd] ? (j1 <= 64 ? "TS(" : "TSX(") : (j1 <= 64 ? "TU(" : "TUX(");
+    o << "u32 " << pout << "; { u32 t_; " << mac << "t_, w" << f / M->jp.per_word << ", " << sel(f) << ", " << j1
+      << "); " << pout << " = __builtin_amdgcn_alignbit(" << pin << ", t_, 31); }\n";
   }
 
   // depth-first over the nodes whose subtree holds groups of [a, b)
+  // pattern variables of the current node's ancestors and itself: chain[k]
+  // holds the raw splits of the first k + 1 nodes of the path
+  std::vector<std::string> chain;
+  struct ChainPush {
+    std::vector<std::string> &c;
+    ChainPush(std::vector<std::string> &c_, const std::string &v) : c(c_) { c.push_back(v); }
+    ~ChainPush() { c.pop_back(); }
+  };
+
+  // Table slot of a unit's index `idx` of `bits` bits: the explain tables store
+  // entry I at I ^ (I >> 3) ^ (I >> 6) (a bijection), which spreads the entries
+  // that share their low three bits (one group of LDS banks for 16-byte rows)
+  // over all groups.  I >> 3 and I >> 6 are the patterns of two ancestors,
+  // already in registers, so the slot costs one three-input XOR.
+  std::string slot(const std::string &idx, int bits) {
+    std::vector<std::string> t{idx};
+    for (int k = 3; k < bits; k += 3) t.push_back(chain[(size_t)(bits - k - 1)]);
+    if (t.size() == 1) return idx;
+    const std::string v = "z" + idx;
+    if (t.size() == 2) o << "const u32 " << v << " = " << t[0] << " ^ " << t[1] << ";\n";
+    else o << "const u32 " << v << " = __builtin_amdgcn_bitop3_b32(" << t[0] << ", " << t[1] << ", " << t[2] << ", 0x96);\n";
+    return v;
+  }
+
   void node(int64_t nd, const std::string &pin) {
     if (!(ix.gmin[(size_t)nd] < b && ix.gmax[(size_t)nd] >= a)) return;
     const std::string pl = "p" + std::to_string(nd);
     test(nd, pl, pin);
+    ChainPush push(chain, pl);
     const int64_t base = M->node_offset[(size_t)M->groups[(size_t)ix.gmin[(size_t)nd]].tree];
     const int64_t L = base + M->left[(size_t)nd], R = base + M->right[(size_t)nd];
     if (on_quad && ix.quad_of[(size_t)nd] >= 0) {
@@ -433,8 +462,9 @@ struct CountGen {
     const int f = M->feature[(size_t)nd];
     const int id = uid++;
     const std::string S = "S" + std::to_string(id);
-    o << "u64 " << S << "; " << (M->default_left[(size_t)nd] ? "NDMS(" : "NDM(") << S << ", w" << f / M->jp.per_word
-      << ", " << sel(f) << ", " << M->jp.rank[(size_t)nd] << ");\n";
+    const int j = M->jp.rank[(size_t)nd];
+    const char *mac = M->default_left[(size_t)nd] ? (j <= 64 ? "NDMS(" : "NDMSX(") : (j <= 64 ? "NDM(" : "NDMX(");
+    o << "u64 " << S << "; " << mac << S << ", w" << f / M->jp.per_word << ", " << sel(f) << ", " << j << ");\n";
     const std::string sl = "sl" + std::to_string(id), sh = "sh" + std::to_string(id);
     o << "const u32 " << sl << " = (u32)" << S << ", " << sh << " = (u32)(" << S << " >> 32);\n";
     const int64_t base = M->node_offset[(size_t)M->groups[(size_t)ix.gmin[(size_t)nd]].tree];
@@ -512,8 +542,12 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
   for (const Group &g : M->groups) maxd = std::max(maxd, g.depth);
   o << kPreamble;
   o << "typedef unsigned long long u64;\n"
-    << "#define NDM(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n"
-    << "#define NDMS(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n";
+    // rank <= j as a wave mask; j <= 64 is an inline constant (NDM/NDMS), larger
+    // ones come in an SGPR (NDMX/NDMSX)
+    << "#define NDM(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, \" #j \" src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w))\n"
+    << "#define NDMS(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), \" #j \" src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w))\n"
+    << "#define NDMX(S, w, sel, j) asm(\"v_cmp_le_u32_sdwa %0, %1, %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n"
+    << "#define NDMSX(S, w, sel, j) asm(\"v_cmp_le_i32_sdwa %0, sext(%1), %2 src0_sel:\" sel \" src1_sel:DWORD\" : \"=s\"(S) : \"v\"(w), \"s\"(j))\n";
   o << "extern \"C\" __global__ __launch_bounds__(" << P.hist_bound
     << ") void wdf_hist_spec(const u32* __restrict__ codes, i64 ldc, i64 m, i64 tiles_per_block, u32* __restrict__ hist, const u32* __restrict__ perm, int live) {\n"
     << "  __shared__ u32 lh[" << P.hist_cap << "];\n"
@@ -717,8 +751,9 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
       pending.clear();
       npending = 0;
     };
-    auto gather = [&](const XUnit &x, const std::string &p, const std::vector<const PathNode *> &pos) {
+    auto gather = [&](const XUnit &x, const std::string &pidx, const std::vector<const PathNode *> &pos) {
       const int64_t E = (int64_t)1 << (x.depth + x.quad);
+      const std::string p = gen.slot(pidx, x.depth + x.quad);
       static const char *C[4] = {"x", "y", "z", "w"};
       std::ostringstream adds;
       for (int j = 0; 4 * j < x.nv; ++j) {
