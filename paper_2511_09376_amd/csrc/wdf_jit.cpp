@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -671,6 +672,16 @@ void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char
 
 constexpr int kGatherBatch = 4;  // explain units whose table reads are in flight together
 
+// Unrolled copy of n16 16-byte pieces from tab + t0 to LDS at dst_off floats:
+// full chunks of nt pieces unconditionally, the last one for the threads it covers.
+void emit_stage_copy(std::ostream &o, int64_t t0, int64_t dst_off, int64_t n16, int nt) {
+  o << "  { const float* s_ = tab + " << t0 << "; float* d_ = lds + " << dst_off << ";";
+  int64_t c = 0;
+  for (; c + nt <= n16; c += nt) o << " STAGE_PIECE(s_, d_, " << c << ");";
+  if (c < n16) o << " if (threadIdx.x < " << (n16 - c) << "u) STAGE_PIECE(s_, d_, " << c << ");";
+  o << " }\n";
+}
+
 std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   const JitPlan &P = M->jp;
   const int F = M->n_features;
@@ -681,16 +692,16 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   o << kPreamble;
   o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n"
     << "#define EXPLAIN_NAME " << explain_kernel_name(P) << "\n"
-    << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
+    << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
+    << "typedef const __attribute__((address_space(3))) vf4* lvf4;  // an LDS address (32 bits)\n";
   o << R"(
-__device__ __forceinline__ void stage_copy(const float* __restrict__ src, float* dst, int n16) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave * 64; c < n16; c += NT) {
-    if (c + lane < n16)
-      __builtin_amdgcn_global_load_lds((const void*)(src + 4 * (c + lane)),
-                                       (__attribute__((address_space(3))) void*)(dst + 4 * c), 16, 0, 0);
-  }
-}
+// One 16-byte piece per thread and chunk of NT pieces, straight from global
+// memory into LDS: piece c + thread of chunk k lands at dst + 4 (c + thread).
+// The stages' sizes are constants, so the copies are unrolled: the uniform
+// parts of the addresses stay in scalar registers.
+#define STAGE_PIECE(src, dst, c) \
+  __builtin_amdgcn_global_load_lds((const void*)(((src) + 4 * (c)) + 4u * threadIdx.x), \
+                                   (__attribute__((address_space(3))) void*)((dst) + 4 * (c) + wbase4), 16, 0, 0)
 // one row per lane, one tile of NT rows per block
 extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __restrict__ X, i64 ldx,
                                                                      const float* __restrict__ tab,
@@ -698,6 +709,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
                                                                      float* __restrict__ phi, i64 ldphi, i64 n, int live) {
   __shared__ __attribute__((aligned(16))) float lds[2 * SF];
   const u32 zero = 0u;
+  const u32 wbase4 = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u) * 4u;  // the wave's first piece, in floats
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
 )";
@@ -717,7 +729,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   // thresholds in the second stage buffer when they fit there, so that the
   // first stage loads during the rank search; else across both buffers
   const bool thr_hi = P.thr_in_lds && (int64_t)P.thr_pad.size() <= P.stage_floats;
-  if (thr_hi) o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n";
+  if (thr_hi) emit_stage_copy(o, t0, 0, n16, P.nt_explain);
   if (P.thr_in_lds)
     o << "  float* lthr = lds + " << (thr_hi ? P.stage_floats : 0) << ";\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
@@ -726,13 +738,15 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
   o << "  float sink = 0.f;  // unused table components (zeros)\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
-  if (!thr_hi) o << "  stage_copy(tab + " << t0 << ", lds, " << n16 << ");\n";
+  if (!thr_hi) emit_stage_copy(o, t0, 0, n16, P.nt_explain);
   o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
+  o << "  LDS_BASES\n";
+  std::set<int64_t> lds_bases;  // 32 KiB steps of the LDS the gathers address from a base register
   for (size_t s = 0; s < S.size(); ++s) {
     const int buf = (int)(s & 1);
     if (s + 1 < S.size()) {
       stage_span(s + 1, t0, n16);
-      o << "  stage_copy(tab + " << t0 << ", lds + " << ((1 - buf) * P.stage_floats) << ", " << n16 << ");\n";
+      emit_stage_copy(o, t0, (int64_t)(1 - buf) * P.stage_floats, n16, P.nt_explain);
     }
     const int64_t sbase = P.xunits[(size_t)unit_of[(size_t)S[s].first]].dst;
     // One 16-byte read per float4 plane returns four values of the entry;
@@ -761,8 +775,19 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
         for (int c = 0; c < 4 && 4 * j + c < x.nv; ++c) any = any || pos[(size_t)(4 * j + c)]->first;
         if (!any) continue;
         const std::string gv = "g" + std::to_string(greg++);
-        o << "const vf4 " << gv << " = ((const vf4*)(lds + " << (buf * P.stage_floats + (x.dst - sbase)) << ") + " << p
-          << ")[" << j * E << "];\n";
+        // ds_read's offset field holds 16 bits: a unit whose last plane ends
+        // past 64 KiB is addressed from the opaque base below it (lb<k>: LDS
+        // byte offset k * 32 KiB), so its address stays one shift-add
+        const int64_t ofs = buf * P.stage_floats + (x.dst - sbase);  // floats
+        const int64_t last_end = 4 * (ofs + 4 * (int64_t)((x.nv + 3) / 4 - 1) * E + 4 * E);
+        if (last_end <= 65536) {
+          o << "const vf4 " << gv << " = ((const vf4*)(lds + " << ofs << ") + " << p << ")[" << j * E << "];\n";
+        } else {
+          const int64_t k = 4 * ofs / 32768;
+          lds_bases.insert(k);
+          o << "const vf4 " << gv << " = (lb" << k << " + " << (ofs - k * 8192) / 4 << " + " << p << ")[" << j * E
+            << "];\n";
+        }
         for (int c = 0; c < 4; ++c) {
           const bool real = 4 * j + c < x.nv && pos[(size_t)(4 * j + c)]->first;
           if (real) adds << " f" << pos[(size_t)(4 * j + c)]->feat << " += " << gv << "." << C[c] << ";";
@@ -801,6 +826,18 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     for (int f = 0; f < F; ++f)
       if (touched[(size_t)f]) o << "  asm volatile(\"\" : \"+v\"(f" << f << "));\n";
     if (s + 1 < S.size()) o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
+  }
+  {
+    // opaque base registers (the compiler would otherwise rebuild each
+    // constant address past 64 KiB with an extra move)
+    std::ostringstream b;
+    for (int64_t k : lds_bases)
+      b << "lvf4 lb" << k << " = (lvf4)(lds + " << k * 8192 << "); asm(\"\" : \"+v\"(lb" << k << "));";
+    std::string body = o.str();
+    const size_t at = body.find("  LDS_BASES\n");
+    body.replace(at, std::strlen("  LDS_BASES\n"), "  " + b.str() + "\n");
+    o.str("");
+    o << body;
   }
   o << "  if (live == 2) phi[row] = sink;  // never (live is 1): keeps the sink's reads whole\n";
   o << "  if (row < n) {\n";
