@@ -2,19 +2,20 @@
 // background summary.
 //
 // Requests (1..max_rows rows of caller-owned host data) wait in a FIFO queue.
-// A worker thread owns a fixed set of batch slots, each with pinned host
-// staging and device buffers for batch_rows rows of X and phi, a stream and
-// events; the number of slots is what the memory budget pays for (at most
-// four).  Whenever a slot is free the worker takes the oldest queued requests
-// that fit in batch_rows rows, has the copy threads pack their rows into the
-// slot's staging, then copies the batch in, runs wdf_explain and copies phi
-// back, all asynchronously on the slot's stream, so the batches of different
-// slots overlap on the device and with the packing of the next batch.  A
-// slot whose last event has completed is drained: the copy threads unpack
-// each request's rows into its caller's buffer, and its latency (submit to
-// result on host) is recorded.  Every row is explained independently of the
-// others in its batch, so a request's result is bit-identical alone and in
-// any mix.
+// The server owns a fixed set of batch slots, each with pinned host staging
+// and device buffers for batch_rows rows of X and phi, a stream and events;
+// the number of slots is what the memory budget pays for (at most four).  A
+// worker thread takes a free slot and the oldest queued requests that fit in
+// it, has its copy threads pack their rows into the slot's staging, then
+// copies the batch in, runs wdf_explain and copies phi back, all
+// asynchronously on the slot's stream, so the batches of different slots
+// overlap on the device.  A completion thread takes launched slots in launch
+// order, waits for each one's last event, has its own copy threads unpack
+// each request's rows into its caller's buffer, records the requests'
+// latencies (submit to result on host) and frees the slot; packing the next
+// batch and unpacking the last one thus run at the same time.  Every row is
+// explained independently of the others in its batch, so a request's result
+// is bit-identical alone and in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -139,16 +140,17 @@ struct wdf_server {
   int queue_cap = 0;
   bool one_per_launch = false;
   std::vector<Slot> slots;
-  std::unique_ptr<CopyPool> pool;
+  std::unique_ptr<CopyPool> pack_pool, unpack_pool;
   int copy_parts = 1;
 
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_launched;
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> pending;
+  std::deque<Slot *> launched;  // slots on the device, in launch order
   uint64_t next_ticket = 1, next_seq = 1;
-  bool stop = false, paused = false;
-  std::thread worker;
+  bool stop = false, paused = false, worker_done = false;
+  std::thread worker, completer;
 
   // statistics; latencies of the most recent kLatencyWindow requests (a
   // ring once full), so that a long-running server's memory stays bounded
@@ -163,6 +165,7 @@ struct wdf_server {
   int worker_error = WDF_OK;
 
   void run();
+  void complete();
   void launch(Slot &s);
   void drain(Slot &s);
   // request offsets inside a slot's batch
@@ -180,7 +183,7 @@ void wdf_server::launch(Slot &s) {
   const std::vector<int64_t> off = offsets(s);
   const auto t0 = Clock::now();
   const size_t ld = (size_t)batch_rows;
-  pool->run(copy_parts, [&](int p) {
+  pack_pool->run(copy_parts, [&](int p) {
     const int f0 = (int)((int64_t)F * p / copy_parts), f1 = (int)((int64_t)F * (p + 1) / copy_parts);
     for (size_t i = 0; i < s.reqs.size(); ++i) {
       const Request &r = *s.reqs[i];
@@ -215,11 +218,13 @@ void wdf_server::launch(Slot &s) {
       r->done = true;
     }
     s.reqs.clear();
+    s.busy = false;
     cv_done.notify_all();
     return;
   }
-  s.busy = true;
   s.seq = next_seq++;
+  launched.push_back(&s);
+  cv_launched.notify_one();
 }
 
 void wdf_server::drain(Slot &s) {
@@ -228,7 +233,7 @@ void wdf_server::drain(Slot &s) {
   const std::vector<int64_t> off = offsets(s);
   const auto t0 = Clock::now();
   const size_t ld = (size_t)batch_rows;
-  pool->run(copy_parts, [&](int p) {
+  unpack_pool->run(copy_parts, [&](int p) {
     const int f0 = (int)((int64_t)F * p / copy_parts), f1 = (int)((int64_t)F * (p + 1) / copy_parts);
     for (size_t i = 0; i < s.reqs.size(); ++i) {
       const Request &r = *s.reqs[i];
@@ -263,49 +268,58 @@ void wdf_server::drain(Slot &s) {
 
 void wdf_server::run() {
   (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lock(mu);
   for (;;) {
-    // 1. fill free slots from the queue (FIFO; a batch takes the oldest
-    //    requests that fit in batch_rows rows), unless paused
-    std::vector<Slot *> to_launch;
-    {
-      std::lock_guard<std::mutex> lock(mu);
-      for (auto &s : slots) {
-        if (paused || s.busy || queue.empty()) continue;
-        int64_t rows_in = 0;
-        while (!queue.empty() && rows_in + queue.front()->n <= batch_rows) {
-          rows_in += queue.front()->n;
-          s.reqs.push_back(queue.front());
-          queue.pop_front();
-          if (one_per_launch) break;
-        }
-        if (!s.reqs.empty()) to_launch.push_back(&s);
-      }
-    }
-    for (Slot *s : to_launch) launch(*s);
-    // 2. drain every finished slot
+    // a free slot and queued requests (FIFO; a batch takes the oldest
+    // requests that fit in batch_rows rows), unless paused
+    Slot *free_slot = nullptr;
     for (auto &s : slots)
-      if (s.busy && hipEventQuery(s.ev[3]) == hipSuccess) drain(s);
-    // 3. wait for something to do
-    Slot *oldest = nullptr;
-    bool any_free = false;
-    for (auto &s : slots) {
-      if (!s.busy) any_free = true;
-      else if (!oldest || s.seq < oldest->seq) oldest = &s;
-    }
-    std::unique_lock<std::mutex> lock(mu);
-    if (!oldest) {
-      cv_work.wait(lock, [&] { return stop || (!paused && !queue.empty()); });
-      if (stop && (queue.empty() || paused)) break;
-    } else if (!any_free || paused || queue.empty()) {
-      // a batch is in flight and nothing can be admitted: wait for the
-      // oldest batch, or shortly for a new request when a slot is free
-      if (!any_free || paused) {
-        lock.unlock();
-        (void)hipEventSynchronize(oldest->ev[3]);
-      } else {
-        cv_work.wait_for(lock, std::chrono::microseconds(50), [&] { return stop || !queue.empty(); });
+      if (!s.busy) {
+        free_slot = &s;
+        break;
       }
+    if (stop && queue.empty()) break;
+    if (paused && !stop) {
+      cv_work.wait(lock);
+      continue;
     }
+    if (queue.empty()) {
+      cv_work.wait(lock);
+      continue;
+    }
+    if (!free_slot) {
+      cv_done.wait(lock);  // the completion thread frees slots
+      continue;
+    }
+    Slot &s = *free_slot;
+    int64_t rows_in = 0;
+    while (!queue.empty() && rows_in + queue.front()->n <= batch_rows) {
+      rows_in += queue.front()->n;
+      s.reqs.push_back(queue.front());
+      queue.pop_front();
+      if (one_per_launch) break;
+    }
+    s.busy = true;
+    lock.unlock();
+    launch(s);  // packs without the lock, takes it to hand the slot over
+    lock.lock();
+  }
+  worker_done = true;
+  cv_launched.notify_all();
+}
+
+void wdf_server::complete() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lock(mu);
+  for (;;) {
+    cv_launched.wait(lock, [&] { return !launched.empty() || worker_done; });
+    if (launched.empty()) break;  // the worker has stopped and every batch is drained
+    Slot *s = launched.front();
+    launched.pop_front();
+    lock.unlock();
+    (void)hipEventSynchronize(s->ev[3]);
+    drain(*s);  // unpacks without the lock, takes it to record and free the slot
+    lock.lock();
   }
 }
 
@@ -343,7 +357,8 @@ extern "C" int wdf_server_create(const wdf_bg *bg, const wdf_server_config *cfg,
   S->paused = (cfg->flags & WDF_SERVE_START_PAUSED) != 0;
   const int threads = cfg->copy_threads > 0 ? cfg->copy_threads : 4;
   S->copy_parts = std::min(threads, F);
-  S->pool.reset(new CopyPool(S->copy_parts));
+  S->pack_pool.reset(new CopyPool(S->copy_parts));
+  S->unpack_pool.reset(new CopyPool(S->copy_parts));
   S->slots.resize(n_slots);
   const size_t bytes = (size_t)F * (size_t)slot_rows * sizeof(float);
   for (auto &s : S->slots) {
@@ -362,6 +377,7 @@ extern "C" int wdf_server_create(const wdf_bg *bg, const wdf_server_config *cfg,
   }
   wdf_server *raw = S.release();
   raw->worker = std::thread([raw] { raw->run(); });
+  raw->completer = std::thread([raw] { raw->complete(); });
   *out = raw;
   return WDF_OK;
 }
@@ -469,7 +485,9 @@ extern "C" void wdf_server_destroy(wdf_server *srv) {
     srv->paused = false;  // queued requests are explained before the worker stops
   }
   srv->cv_work.notify_all();
+  srv->cv_done.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
+  if (srv->completer.joinable()) srv->completer.join();
   (void)hipSetDevice(srv->device);
   for (auto &s : srv->slots) {
     if (s.stream) (void)hipStreamSynchronize(s.stream);
