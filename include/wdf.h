@@ -330,35 +330,45 @@ int64_t wdf_debug_iv_source(const wdf_model_desc *desc, char *out, int64_t cap);
 /* Launch configurations measured by wdf_model_autotune (times in ms, -1 when
  * not measured). */
 typedef struct {
-  int quads;                  /* chosen explain gather: 1 quad tables, 0 pair tables */
+  int quads;                  /* chosen explain gather: the sibling pairs of depth <= quads are merged
+                                 into quad tables, 0 = pair tables only (WDF_MAX_DEPTH: all) */
+  int explain_rows;           /* chosen explain tile: 512 (one block per CU, all of the LDS) or 256
+                                 rows per block (two per CU, half of it each) */
   int hist_rounds;            /* chosen histogram grid: blocks per CU over the launch */
   int hist_threads;           /* chosen histogram block: 512, 768 or 1024 threads (at most the
                                  launch bound the model's histogram kernel was compiled for) */
-  float explain_ms[2];        /* explain time with [0] pair tables, [1] quad tables */
+  float explain_ms[WDF_MAX_DEPTH + 1];  /* explain time per quads value, 512-row tiles */
+  float explain_rows_ms[2];   /* explain time with the chosen gather: [0] 512-row, [1] 256-row tiles */
   float hist_ms[3][9];        /* histogram time with [512, 768, 1024 threads][hist_rounds = 1..8] */
 } wdf_tuning;
 
 /* Measure the model's specialised kernels on the caller's data and keep the
- * fastest configuration for later calls: the explain gather (pair or quad
- * tables, a compile-time choice: each variant is generated and compiled once
- * and cached) and the histogram grid and block size (launch-time choices).  B [F][ldb] (m
- * rows) and X [F][ldx] (n rows) are device pointers; a sample of a few hundred
- * thousand rows is enough.  Runs and synchronises on hip_stream.  No summary
- * of the model may exist during the call (summaries hold tables laid out for
- * the gather in use).  Errors: INVALID_ARG (NULL, sizes, summaries exist),
- * UNSUPPORTED (the model runs the generic kernels), COMPILE, OOM, DEVICE. */
+ * fastest configuration for later calls: the explain gather (pair tables
+ * only, quads for the sibling pairs of depth <= 6 when deeper ones exist, or
+ * quads for all), the explain tile (512 or 256 rows per
+ * block) - compile-time choices, each variant generated, compiled once (the
+ * candidates in parallel) and cached - and the histogram grid and block size
+ * (launch-time choices).  B [F][ldb] (m rows) and X [F][ldx] (n rows) are
+ * device pointers; a sample of a few hundred thousand rows is enough.  Runs
+ * and synchronises on hip_stream.  No summary of the model may exist during
+ * the call (summaries hold tables laid out for the gather in use).
+ * Errors: INVALID_ARG (NULL, sizes, summaries exist), UNSUPPORTED (the model
+ * runs the generic kernels), COMPILE, OOM, DEVICE. */
 int wdf_model_autotune(wdf_model *model, const float *B, int64_t m, int64_t ldb, const float *X, int64_t n,
                        int64_t ldx, void *hip_stream, wdf_tuning *out);
 
 /* Apply a launch configuration measured earlier (by wdf_model_autotune, in
  * this process or another, and kept by the caller) without measuring again:
- * t->quads selects the explain gather (0 pair tables, 1 quad tables, -1 the
- * current one; each variant is compiled once and cached), t->hist_threads (a multiple of 64 in
+ * t->quads selects the explain gather (sibling pairs of depth <= quads merged
+ * into quads, 0 pair tables only, -1 the current one), t->explain_rows the
+ * explain tile (512 or 256 rows, 0 the current one; each variant is
+ * compiled once and cached), t->hist_threads (a multiple of 64 in
  * [64, the launch bound the model's histogram kernel was compiled for]) and
  * t->hist_rounds (1..64 blocks per CU over the launch) the histogram grid.
  * The time fields are ignored.  No summary of the model may exist during the
- * call.  Results do not depend on the configuration: the histograms are exact
- * counts in any grid, and both gathers add the same table values.
+ * call.  The histograms are exact counts in any grid; the gathers and tiles
+ * add the same table values, the gathers in another order (phi agrees to
+ * rounding).
  * Errors: INVALID_ARG (NULL, a field out of range, summaries exist),
  * UNSUPPORTED (the model runs the generic kernels), COMPILE, OOM, DEVICE. */
 int wdf_model_set_tuning(wdf_model *model, const wdf_tuning *t);

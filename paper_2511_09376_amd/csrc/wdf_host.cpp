@@ -460,7 +460,7 @@ extern "C" int wdf_model_load(wdf_ctx *ctx, const wdf_model_desc *desc, int kern
   }
   if ((rc = upload_model(M.get()))) return rc;
   if (kernel != WDF_KERNEL_GENERIC) {
-    M->jp.quads = quads;
+    M->jp.quad_depth = quads ? WDF_MAX_DEPTH : 0;
     rc = jit_build(M.get());
     if (rc != WDF_OK) {
       if (kernel == WDF_KERNEL_SPECIALISED) return rc;
@@ -1127,7 +1127,7 @@ extern "C" int64_t wdf_debug_specialised_source(const wdf_model_desc *desc, int 
     wdf_model M;
     int rc = validate_and_layout(desc, &M);
     if (rc) return rc;
-    M.jp.quads = (kernel & WDF_KERNEL_PAIRS) == 0;
+    M.jp.quad_depth = (kernel & WDF_KERNEL_PAIRS) == 0 ? WDF_MAX_DEPTH : 0;
     std::string src;
     if ((rc = jit_source(&M, do_compile != 0, src))) return rc;
     if (out && cap > (int64_t)src.size()) std::memcpy(out, src.c_str(), src.size() + 1);

@@ -69,7 +69,7 @@ struct JitPlan {
   std::vector<XUnit> xunits;    // explain-table units in group order
   std::vector<int64_t> unit_g0; // first group of every unit (plus a final G)
   int64_t xtab_size = 0;
-  bool quads = true;            // merge sibling pair groups into quads
+  int quad_depth = WDF_MAX_DEPTH;  // pair groups of depth <= this merge into quads (0: pair tables only)
   bool thr_in_lds = true;       // thresholds searched in LDS (else in global memory)
   int hist_rounds = 2;          // histogram blocks per CU over the whole launch
   std::vector<int32_t> pad_meta;  // per feature: thr_pad offset, steps (the quantizer's view)
@@ -183,6 +183,11 @@ struct wdf_graph {
 namespace wdf {
 // Model-specialised kernels (wdf_jit.cpp).
 int jit_build(wdf_model *M);
+// compile (in parallel) and cache the programs (source, kernel name) not yet cached
+int jit_compile_all(wdf_model *M, const std::vector<std::pair<std::string, std::string>> &progs);
+// the explain-kernel source of the model's current plan (plans the model)
+int jit_explain_source(wdf_model *M, std::string &src);
+const char *jit_explain_name(const wdf_model *M);
 // the specialised interaction kernel (compiled on first use; WDF_E_UNSUPPORTED
 // when the model is too large for it)
 int jit_build_iv(wdf_model *M);

@@ -23,6 +23,7 @@
 #include <set>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "wdf.h"
@@ -190,7 +191,7 @@ int make_plan(wdf_model *M) {
   for (int64_t g = 0; g < G;) {
     const Group &ga = M->groups[(size_t)g];
     bool quad = false;
-    if (P.quads && g + 1 < G && ga.depth >= 2 && ga.col_r >= 0) {
+    if (ga.depth <= P.quad_depth && g + 1 < G && ga.depth >= 2 && ga.col_r >= 0) {
       const Group &gb = M->groups[(size_t)g + 1];
       if (gb.depth == ga.depth && gb.col_r >= 0 && gb.tree == ga.tree) {
         const size_t la = (size_t)ga.path_off + (size_t)ga.depth, lb = (size_t)gb.path_off + (size_t)gb.depth;
@@ -254,7 +255,7 @@ typedef long long i64;
 )";
 
 // the explain kernel is named by its gather, so that profiles tell the variants apart
-const char *explain_kernel_name(const JitPlan &P) { return P.quads ? "wdf_explain_quads" : "wdf_explain_pairs"; }
+const char *explain_kernel_name(const JitPlan &P) { return P.quad_depth > 0 ? "wdf_explain_quads" : "wdf_explain_pairs"; }
 
 struct TreeIndex {
   // per global node: group indices hanging off it, and the group range below it
@@ -884,6 +885,13 @@ int jit_sources(wdf_model *M, std::string &hist_src, std::string &explain_src) {
   return WDF_OK;
 }
 
+const char *jit_explain_name(const wdf_model *M) { return explain_kernel_name(M->jp); }
+
+int jit_explain_source(wdf_model *M, std::string &src) {
+  std::string h;
+  return jit_sources(M, h, src);
+}
+
 int jit_source(wdf_model *M, bool do_compile, std::string &src) {
   std::string h, x;
   int rc = jit_sources(M, h, x);
@@ -928,6 +936,36 @@ int spill_bytes(hipFunction_t fn) {
 
 }  // namespace
 
+int jit_compile_all(wdf_model *M, const std::vector<std::pair<std::string, std::string>> &progs) {
+  // hipRTC compiles of different programs are independent: the ones not yet
+  // cached are compiled on threads of their own, then loaded on this thread
+  // (which has the model's device current)
+  std::vector<size_t> todo;
+  for (size_t i = 0; i < progs.size(); ++i) {
+    bool dup = false;
+    for (size_t j : todo) dup = dup || progs[j].first == progs[i].first;
+    if (!dup && !cached_part(M, progs[i].first)) todo.push_back(i);
+  }
+  std::vector<std::vector<char>> code(todo.size());
+  std::vector<int> rcs(todo.size(), WDF_OK);
+  std::vector<std::string> errs(todo.size());
+  std::vector<std::thread> th;
+  for (size_t k = 0; k < todo.size(); ++k)
+    th.emplace_back([&, k] {
+      rcs[k] = compile(progs[todo[k]].first, code[k]);
+      if (rcs[k]) errs[k] = wdf_last_error();  // the error text is thread-local
+    });
+  for (auto &t : th) t.join();
+  for (size_t k = 0; k < todo.size(); ++k)
+    if (rcs[k]) return set_error(rcs[k], "%s", errs[k].c_str());
+  for (size_t k = 0; k < todo.size(); ++k) {
+    std::shared_ptr<JitPart> part;
+    const int rc = load_part(M, progs[todo[k]].first, code[k], progs[todo[k]].second.c_str(), part);
+    if (rc) return rc;
+  }
+  return WDF_OK;
+}
+
 int jit_build(wdf_model *M) {
   if (M->n_nodes > kMaxSpecialisedNodes)
     return set_error(WDF_E_UNSUPPORTED, "specialised kernels: %lld nodes exceeds %lld", (long long)M->n_nodes,
@@ -936,17 +974,11 @@ int jit_build(wdf_model *M) {
   int rc = jit_sources(M, hsrc, xsrc);
   if (rc) return rc;
   auto mod = std::make_shared<JitModule>();
+  // two programs, cached apart: variants that differ in one part (the explain
+  // gather, the histogram bound) reuse the other
+  if ((rc = jit_compile_all(M, {{hsrc, "wdf_hist_spec"}, {xsrc, explain_kernel_name(M->jp)}}))) return rc;
   mod->hist_part = cached_part(M, hsrc);
   mod->explain_part = cached_part(M, xsrc);
-  {
-    // two programs, cached apart: variants that differ in one part (the
-    // explain gather, the histogram bound) reuse the other
-    std::vector<char> ch, cx;
-    if (!mod->hist_part && (rc = compile(hsrc, ch))) return rc;
-    if (!mod->explain_part && (rc = compile(xsrc, cx))) return rc;
-    if (!mod->hist_part && (rc = load_part(M, hsrc, ch, "wdf_hist_spec", mod->hist_part))) return rc;
-    if (!mod->explain_part && (rc = load_part(M, xsrc, cx, explain_kernel_name(M->jp), mod->explain_part))) return rc;
-  }
   // A histogram kernel that spills registers at its launch bound is rebuilt
   // once at 512 threads (256 VGPRs); the explain program is kept.
   if (M->jp.hist_bound > 512 && spill_bytes(mod->hist_part->fn) > 0) {

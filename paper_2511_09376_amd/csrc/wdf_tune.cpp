@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <memory>
+#include <string>
+#include <vector>
 
 #include "wdf.h"
 #include "wdf_dev.h"
@@ -55,6 +57,7 @@ extern "C" int wdf_model_autotune(wdf_model *M, const float *B, int64_t m, int64
   hipStream_t s = (hipStream_t)hip_stream;
   *out = wdf_tuning{};
   for (float &t : out->explain_ms) t = -1.f;
+  for (float &t : out->explain_rows_ms) t = -1.f;
   for (auto &row : out->hist_ms)
     for (float &t : row) t = -1.f;
   const int reps = 3;
@@ -95,27 +98,71 @@ extern "C" int wdf_model_autotune(wdf_model *M, const float *B, int64_t m, int64
     out->hist_threads = best_t;
   }
 
-  // explain gather: a compile-time choice; each variant gets a summary of B
+  // explain gather and tile: compile-time choices.  Candidate gathers: pair
+  // tables only, quads for the sibling pairs of depth <= 6 (when deeper pairs
+  // exist: their quad tables are 4 to 16 times larger), and quads for all;
+  // their programs are compiled in parallel, then each gets a summary of B
+  // and is timed.
   DevBuf phi;
   if ((rc = phi.alloc((size_t)M->n_features * (size_t)n * sizeof(float)))) return rc;
-  const bool keep_quads = M->jp.quads;
-  for (int q : {0, 1}) {
-    M->jp.quads = q != 0;
-    if ((rc = jit_build(M))) break;
-    wdf_bg *bg = nullptr;
-    if ((rc = wdf_background_load(M, B, m, ldb, 1, WDF_SHAPLEY, s, &bg))) break;
-    const float ms = time_runs(s, reps, [&] { return wdf_explain(bg, X, n, ldx, phi.as<float>(), n, s); }, rc);
-    wdf_bg_destroy(bg);
-    if (rc) break;
-    out->explain_ms[q] = ms;
-  }
-  if (rc) {  // back to the plan the model had (its module is cached)
-    M->jp.quads = keep_quads;
+  const int keep_q = M->jp.quad_depth, keep_bpc = M->jp.explain_bpc;
+  int max_pair = 0;
+  for (const Group &g : M->groups)
+    if (g.col_r >= 0) max_pair = std::max(max_pair, g.depth);
+  std::vector<int> qs{0};
+  if (max_pair > 6) qs.push_back(6);
+  if (max_pair >= 2) qs.push_back(WDF_MAX_DEPTH);
+  auto restore = [&] {  // back to the plan the model had (its programs are cached)
+    M->jp.quad_depth = keep_q;
+    M->jp.explain_bpc = keep_bpc;
     (void)jit_build(M);
+  };
+  auto time_explain = [&](float &ms) {
+    if ((rc = jit_build(M))) return;
+    wdf_bg *bg = nullptr;
+    if ((rc = wdf_background_load(M, B, m, ldb, 1, WDF_SHAPLEY, s, &bg))) return;
+    ms = time_runs(s, reps, [&] { return wdf_explain(bg, X, n, ldx, phi.as<float>(), n, s); }, rc);
+    wdf_bg_destroy(bg);
+  };
+  {
+    std::vector<std::pair<std::string, std::string>> progs;
+    for (int q : qs) {
+      M->jp.quad_depth = q;
+      M->jp.explain_bpc = 1;
+      std::string src;
+      if ((rc = jit_explain_source(M, src))) break;
+      progs.push_back({src, jit_explain_name(M)});
+    }
+    if (!rc) rc = jit_compile_all(M, progs);
+    if (rc) {
+      restore();
+      return rc;
+    }
+  }
+  int best_q = 0;
+  for (int q : qs) {
+    M->jp.quad_depth = q;
+    M->jp.explain_bpc = 1;
+    time_explain(out->explain_ms[q]);
+    if (rc) {
+      restore();
+      return rc;
+    }
+    if (out->explain_ms[q] < out->explain_ms[best_q]) best_q = q;
+  }
+  // the tile: one 512-row block per CU with all of the LDS, or two 256-row
+  // blocks per CU with half of it each
+  out->explain_rows_ms[0] = out->explain_ms[best_q];
+  M->jp.quad_depth = best_q;
+  M->jp.explain_bpc = 2;
+  time_explain(out->explain_rows_ms[1]);
+  if (rc) {
+    restore();
     return rc;
   }
-  M->jp.quads = out->explain_ms[1] <= out->explain_ms[0];
-  out->quads = M->jp.quads ? 1 : 0;
+  M->jp.explain_bpc = out->explain_rows_ms[1] < out->explain_rows_ms[0] ? 2 : 1;
+  out->quads = best_q;
+  out->explain_rows = 512 / M->jp.explain_bpc;
   if ((rc = jit_build(M))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   return WDF_OK;
@@ -127,8 +174,10 @@ extern "C" int wdf_model_set_tuning(wdf_model *M, const wdf_tuning *t) {
   if (M->n_bg.load() != 0)
     return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: %d background summaries of this model exist",
                      M->n_bg.load());
-  if (t->quads < -1 || t->quads > 1)
-    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: quads must be -1, 0 or 1");
+  if (t->quads < -1 || t->quads > WDF_MAX_DEPTH)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: quads must be -1 .. %d", WDF_MAX_DEPTH);
+  if (t->explain_rows != 0 && t->explain_rows != 512 && t->explain_rows != 256)
+    return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: explain_rows must be 0, 256 or 512");
   if (t->hist_threads < 64 || t->hist_threads % 64 || t->hist_threads > M->jp.hist_bound)
     return set_error(WDF_E_INVALID_ARG,
                      "wdf_model_set_tuning: hist_threads %d is not a multiple of 64 in [64, %d] (the compiled bound)",
@@ -136,12 +185,16 @@ extern "C" int wdf_model_set_tuning(wdf_model *M, const wdf_tuning *t) {
   if (t->hist_rounds < 1 || t->hist_rounds > 64)
     return set_error(WDF_E_INVALID_ARG, "wdf_model_set_tuning: hist_rounds %d outside [1, 64]", t->hist_rounds);
   HIP_TRY(hipSetDevice(M->ctx->device));
-  if (t->quads >= 0 && (t->quads != 0) != M->jp.quads) {
-    const bool keep = M->jp.quads;
-    M->jp.quads = t->quads != 0;
+  const int q = t->quads >= 0 ? t->quads : M->jp.quad_depth;
+  const int bpc = t->explain_rows ? 512 / t->explain_rows : M->jp.explain_bpc;
+  if (q != M->jp.quad_depth || bpc != M->jp.explain_bpc) {
+    const int keep_q = M->jp.quad_depth, keep_bpc = M->jp.explain_bpc;
+    M->jp.quad_depth = q;
+    M->jp.explain_bpc = bpc;
     int rc = jit_build(M);
     if (rc) {
-      M->jp.quads = keep;
+      M->jp.quad_depth = keep_q;
+      M->jp.explain_bpc = keep_bpc;
       (void)jit_build(M);  // the previous programs are cached
       return rc;
     }

@@ -105,8 +105,9 @@ def _finalizing() -> bool:
 
 
 class Tuning(C.Structure):
-    _fields_ = [("quads", C.c_int), ("hist_rounds", C.c_int), ("hist_threads", C.c_int),
-                ("explain_ms", C.c_float * 2), ("hist_ms", (C.c_float * 9) * 3)]
+    _fields_ = [("quads", C.c_int), ("explain_rows", C.c_int), ("hist_rounds", C.c_int), ("hist_threads", C.c_int),
+                ("explain_ms", C.c_float * (MAX_DEPTH + 1)), ("explain_rows_ms", C.c_float * 2),
+                ("hist_ms", (C.c_float * 9) * 3)]
 
 
 EXPORTS = [
@@ -309,18 +310,26 @@ class Model:
         _check(lib().wdf_model_autotune(self.h, C.c_void_p(B.data_ptr()), B.shape[1], B.stride(0),
                                         C.c_void_p(X.data_ptr()), X.shape[1], X.stride(0), _stream_handle(stream),
                                         C.byref(t)))
-        return {"gather": "quads" if t.quads else "pairs", "hist_rounds": int(t.hist_rounds),
-                "hist_threads": int(t.hist_threads),
-                "explain_ms": {"pairs": float(t.explain_ms[0]), "quads": float(t.explain_ms[1])},
+        ex = {"pairs": float(t.explain_ms[0]), "quads": float(t.explain_ms[MAX_DEPTH])}
+        ex.update({f"quads<={q}": float(t.explain_ms[q]) for q in range(1, MAX_DEPTH) if t.explain_ms[q] >= 0})
+        return {"gather": "quads" if t.quads else "pairs", "quad_depth": int(t.quads),
+                "explain_rows": int(t.explain_rows), "hist_rounds": int(t.hist_rounds),
+                "hist_threads": int(t.hist_threads), "explain_ms": ex,
+                "explain_rows_ms": {"512": float(t.explain_rows_ms[0]), "256": float(t.explain_rows_ms[1])},
                 "hist_ms": {f"{nt}x{r}": float(t.hist_ms[i][r]) for i, nt in enumerate((512, 768, 1024))
                             for r in range(1, 9) if t.hist_ms[i][r] >= 0}}
 
     def set_tuning(self, tuning: dict):
         """Apply a configuration returned by autotune() (here or in another
-        process: the dict round-trips through JSON) without measuring; only
-        its gather (kept when absent), hist_threads and hist_rounds are used."""
+        process: the dict round-trips through JSON) without measuring; its
+        quad_depth (or gather), explain_rows (each kept when absent),
+        hist_threads and hist_rounds are used."""
         t = Tuning()
-        t.quads = {"quads": 1, "pairs": 0, None: -1}[tuning.get("gather")]
+        if "quad_depth" in tuning:
+            t.quads = int(tuning["quad_depth"])
+        else:
+            t.quads = {"quads": MAX_DEPTH, "pairs": 0, None: -1}[tuning.get("gather")]
+        t.explain_rows = int(tuning.get("explain_rows", 0))
         t.hist_threads = int(tuning["hist_threads"])
         t.hist_rounds = int(tuning["hist_rounds"])
         _check(lib().wdf_model_set_tuning(self.h, C.byref(t)))
