@@ -204,18 +204,20 @@ int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float 
  * [F][ldx >= n]; iv: device [F * F][ldiv >= n], iv[(i * F + j) * ldiv + r]
  * for consumer r, symmetric in (i, j), diagonal 0.  The rows' patterns of
  * every group go to `workspace` (device memory of at least
- * wdf_explain_iv_workspace(bg, n) bytes, owned by the caller, not shared by
- * overlapping calls); then one wave per (64 rows, feature i) adds the pair
- * tables of i's partners j, selected by those patterns, into registers and
- * stores row i of each row's matrix (kernels generated for the model, or a
- * generic kernel walking i's (group, j) work list sorted by j).
+ * wdf_explain_iv_workspace(bg, n) bytes, 16-byte aligned, owned by the
+ * caller, not shared by overlapping calls); then one lane per (row, feature
+ * i) adds the pair tables of i's partners j, selected by those patterns, into
+ * registers and stores row i of each row's matrix (kernels generated for the
+ * model, which stream each feature's tables and the rows' patterns through
+ * LDS, or a generic kernel walking i's (group, j) work list sorted by j).
  * Asynchronous on hip_stream; allocates nothing.
- * Errors: INVALID_ARG (NULL, sizes, small workspace, summary not of an
- * interaction kind), UNSUPPORTED (more than 65535 groups), DEVICE. */
+ * Errors: INVALID_ARG (NULL, sizes, small or misaligned workspace, summary
+ * not of an interaction kind), UNSUPPORTED (more than 65535 groups), DEVICE. */
 int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
                    void *workspace, size_t workspace_bytes, void *hip_stream);
 /* Workspace bytes wdf_explain_iv needs for n rows (one byte per group and
- * row; at least 1).  Errors: INVALID_ARG (NULL summary, n < 0). */
+ * row, the rows rounded up to a multiple of 512; at least 1).
+ * Errors: INVALID_ARG (NULL summary, n < 0). */
 int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -226,7 +228,7 @@ int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n);
  * WDF_NOALLOC_SCRATCH_BYTES bytes that every device the library runs on holds
  * until the process ends; the call allocates nothing and calls no allocating
  * routine.  n rows need wdf_explain_iv_workspace(bg, n) bytes of it (one per
- * group and row): larger calls fail with INVALID_ARG and the row limit in
+ * group and row, rows in blocks of 512): larger calls fail with INVALID_ARG and the row limit in
  * wdf_last_error().  All calls on one device share its array, which keeps the
  * last call's patterns (every byte read is written first, so nothing needs
  * clearing): calls that overlap on one device (different streams, or before

@@ -56,9 +56,16 @@ inline int64_t xunit_floats(const XUnit &u) {
 }
 
 // A unit of the specialised interaction tables: one group and one feature i
-// at its first path position; the pair tables of i with the other first
-// positions (partners, in path order) interleaved by pattern:
-// [plane][pattern][4 partners], zeros after the last partner.
+// at its first path position, with the pair tables of i and each other first
+// position (its partners, in path order).  The tables are indexed by the raw
+// splits r of the group's path (bit 1: the row went left; the pattern is
+// r ^ mask) and stored as planes [plane][slot][width]: 4-wide planes for
+// partners 0..3, 4..7 (a last group of three partners takes a 4-wide plane
+// with one zero), then one 2- or 1-wide plane for a remaining two or one, so
+// that a unit of five partners costs one 16-byte and one 4-byte read.  Entry r
+// sits at slot r ^ (r >> 3) ^ (r >> 6) of every plane (a bijection on d bits),
+// which spreads entries sharing their low three bits (one group of LDS banks
+// for 16-byte rows) over all groups.
 struct IvUnit {
   int64_t src;     // the group's pair tables (interaction-table offset)
   int64_t dst;     // offset in the interleaved tables (floats, multiple of 4)
@@ -66,9 +73,18 @@ struct IvUnit {
   int32_t cnt;     // partners, 1..7
   int32_t q[7];    // pair index of (i, partner s) among the group's position pairs
   int32_t group;   // the group
+  uint32_t mask;   // right turns of the group's path, root first (MSB)
 };
 
-// floats of a unit in the interleaved interaction tables
-inline int64_t ivunit_floats(const IvUnit &u) { return 4 * (int64_t)((u.cnt + 3) / 4) << u.depth; }
+// 4-wide planes of a unit with cnt partners, and the width of its narrow plane (0, 1 or 2)
+constexpr int ivunit_quads(int cnt) { return cnt / 4 + (cnt % 4 == 3 ? 1 : 0); }
+constexpr int ivunit_tail(int cnt) { return cnt % 4 == 3 ? 0 : cnt % 4; }
+// slot of raw index r in every plane
+constexpr uint32_t ivunit_slot(uint32_t r) { return r ^ (r >> 3) ^ (r >> 6); }
+
+// floats of a unit in the interleaved interaction tables (a multiple of 4)
+constexpr int64_t ivunit_floats(const IvUnit &u) {
+  return (((int64_t)(4 * ivunit_quads(u.cnt) + ivunit_tail(u.cnt)) << u.depth) + 3) & ~(int64_t)3;
+}
 
 }  // namespace wdf

@@ -582,6 +582,8 @@ static int iv_layout_host(wdf_model *M, std::vector<int32_t> &ioff, std::vector<
       u.src = M->iv_off[g];
       u.depth = d;
       u.group = (int32_t)g;
+      for (int k = 0; k < d; ++k)
+        if (M->path[(size_t)gr.path_off + k].dir) u.mask |= 1u << (d - 1 - k);
       for (int k2 = 0; k2 < d; ++k2) {
         const PathNode &b = M->path[(size_t)gr.path_off + k2];
         if (k2 == k1 || !b.first) continue;
@@ -966,7 +968,7 @@ extern "C" int wdf_explain(const wdf_bg *bg, const float *X, int64_t n, int64_t 
 
 extern "C" int64_t wdf_explain_iv_workspace(const wdf_bg *bg, int64_t n) {
   if (!bg || n < 0) return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv_workspace: NULL summary or n < 0");
-  return std::max<int64_t>((int64_t)bg->model->groups.size() * n, 1);
+  return std::max<int64_t>((int64_t)bg->model->groups.size() * iv_pattern_stride(n), 1);
 }
 
 extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64_t ldx, float *iv, int64_t ldiv,
@@ -979,9 +981,12 @@ extern "C" int wdf_explain_iv(const wdf_bg *bg, const float *X, int64_t n, int64
   wdf_model *M = bg->model;
   const int64_t G = (int64_t)M->groups.size();
   if (G > 65535) return set_error(WDF_E_UNSUPPORTED, "wdf_explain_iv: %lld groups exceeds 65535", (long long)G);
-  if (!workspace || (int64_t)workspace_bytes < G * n)
+  const int64_t need = wdf_explain_iv_workspace(bg, n);
+  if (!workspace || (int64_t)workspace_bytes < need)
     return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace of %zu bytes, need %lld", workspace_bytes,
-                     (long long)(G * n));
+                     (long long)need);
+  if ((uintptr_t)workspace % 16)
+    return set_error(WDF_E_INVALID_ARG, "wdf_explain_iv: workspace not 16-byte aligned");
   hipStream_t s = pick_stream(M->ctx, hip_stream);
   if (bg->iv_spec) return jit_explain_iv(bg, X, ldx, (uint8_t *)workspace, n, iv, ldiv, s);
   HIP_TRY(launch_explain_iv(M->d_groups.as<Group>(), M->d_path.as<PathNode>(), G, M->d_iv_item_off.as<int32_t>(),
@@ -1000,7 +1005,8 @@ extern "C" int wdf_explain_iv_noalloc(const wdf_bg *bg, const float *X, int64_t 
                      "wdf_explain_iv_noalloc: %lld rows need %lld bytes of pattern scratch, above the library's "
                      "%lld (explain at most %lld rows per call, or pass a workspace to wdf_explain_iv)",
                      (long long)n, (long long)need, (long long)WDF_NOALLOC_SCRATCH_BYTES,
-                     (long long)(WDF_NOALLOC_SCRATCH_BYTES / std::max<int64_t>(need / std::max<int64_t>(n, 1), 1)));
+                     (long long)((int64_t)WDF_NOALLOC_SCRATCH_BYTES /
+                                 std::max<int64_t>((int64_t)bg->model->groups.size(), 1) / 512 * 512));
   // the pattern kernel writes every byte the interaction kernels read, so
   // the scratch needs no clearing between calls
   return wdf_explain_iv(bg, X, n, ldx, iv, ldiv, bg->model->ctx->scratch, WDF_NOALLOC_SCRATCH_BYTES, hip_stream);

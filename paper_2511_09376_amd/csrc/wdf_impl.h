@@ -193,6 +193,9 @@ const char *jit_explain_name(const wdf_model *M);
 int jit_build_iv(wdf_model *M);
 int jit_iv_source(wdf_model *M, std::string &src);  // interaction and pattern kernels (plans the model)
 // patterns of the consumer rows into the workspace pat, then the interaction kernels
+// Row stride of the interaction kernels' pattern workspace: n rounded up to
+// a multiple of 512 (whole blocks of 16-byte pieces for every row block).
+inline int64_t iv_pattern_stride(int64_t n) { return (n + 511) / 512 * 512; }
 int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, int64_t n, float *iv, int64_t ldiv,
                    hipStream_t s);
 int jit_source(wdf_model *M, bool do_compile, std::string &src);

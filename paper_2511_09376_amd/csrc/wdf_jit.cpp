@@ -671,6 +671,18 @@ void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char
   }
 }
 
+// The stage-copy macro of the generated kernels (needs wbase4, the first
+// piece of the thread's wave in floats).
+const char *kStagePiece = R"(
+// One 16-byte piece per thread and chunk of NT pieces, straight from global
+// memory into LDS: piece c + thread of chunk k lands at dst + 4 (c + thread).
+// The stages' sizes are constants, so the copies are unrolled: the uniform
+// parts of the addresses stay in scalar registers.
+#define STAGE_PIECE(src, dst, c) \
+  __builtin_amdgcn_global_load_lds((const void*)(((src) + 4 * (c)) + 4u * threadIdx.x), \
+                                   (__attribute__((address_space(3))) void*)((dst) + 4 * (c) + wbase4), 16, 0, 0)
+)";
+
 constexpr int kGatherBatch = 4;  // explain units whose table reads are in flight together
 
 // Unrolled copy of n16 16-byte pieces from tab + t0 to LDS at dst_off floats:
@@ -695,15 +707,7 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
     << "#define EXPLAIN_NAME " << explain_kernel_name(P) << "\n"
     << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
     << "typedef const __attribute__((address_space(3))) vf4* lvf4;  // an LDS address (32 bits)\n";
-  o << R"(
-// One 16-byte piece per thread and chunk of NT pieces, straight from global
-// memory into LDS: piece c + thread of chunk k lands at dst + 4 (c + thread).
-// The stages' sizes are constants, so the copies are unrolled: the uniform
-// parts of the addresses stay in scalar registers.
-#define STAGE_PIECE(src, dst, c) \
-  __builtin_amdgcn_global_load_lds((const void*)(((src) + 4 * (c)) + 4u * threadIdx.x), \
-                                   (__attribute__((address_space(3))) void*)((dst) + 4 * (c) + wbase4), 16, 0, 0)
-// one row per lane, one tile of NT rows per block
+  o << kStagePiece << R"(// one row per lane, one tile of NT rows per block
 extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __restrict__ X, i64 ldx,
                                                                      const float* __restrict__ tab,
                                                                      const float* __restrict__ thr,
@@ -1024,101 +1028,306 @@ int jit_build(wdf_model *M) {
   return WDF_OK;
 }
 
-// Interaction values, specialised: one wave = 64 rows and one feature i (a
-// case of the switch on blockIdx.y).  For every unit of i (a group where i
-// has a first occurrence), the rows' pattern of the group is read from the
-// workspace and each 16-byte read of the interleaved tables returns the pair
-// values of four partners, added into registers with static indices (one per
-// partner feature of i).  Then the row's iv[i][j] for every j, zeros where i
-// has no pair with j (the diagonal among them).
+// Interaction values, specialised: one block = kIvRows rows (one per lane)
+// and one feature i (a case of the switch on blockIdx.y), two or three
+// blocks per CU.  The units of i (a
+// group where i has a first occurrence) are contiguous in the interleaved
+// tables; they stream through a ring of LDS buffers in stages, each copied
+// straight from global memory into LDS by all waves while earlier stages are
+// read.  Each wave copies its own 64 rows of the units' patterns (one byte
+// per row and unit, from the workspace) into a ring of its own, several
+// chunks ahead: these are cold HBM reads, and no other wave reads them, so
+// they need no barrier, only the wave's own wait.  Per unit and row: the
+// pattern byte from LDS, one 16-byte read per four partners (and one 4- or
+// 8-byte read for a last one or two), each value added into a register with
+// a static index (one per partner feature of i).  Then the row's iv[i][j] for
+// every j, zeros where i has no pair with j (the diagonal among them), with
+// non-temporal stores.
+//
+// Waits are counted: the generator knows every wave's sequence of memory
+// reads into LDS, and before data is used it waits until at most the number
+// of copies issued after it are outstanding (vmcnt; the counter drains in
+// issue order), so later prefetches stay in flight.
 namespace {
 
 int64_t iv_spec_ops(const wdf_model *M) {
   int64_t ops = 0;
-  for (const IvUnit &u : M->iv_units) ops += 1 + (u.cnt + 3) / 4 + u.cnt;
+  for (const IvUnit &u : M->iv_units) ops += 1 + ivunit_quads(u.cnt) + (ivunit_tail(u.cnt) > 0) + u.cnt;
   return ops;
 }
 
-constexpr int kIvBatch = 4;     // units per basic block of the interaction kernels
-constexpr int kIvPerKernel = 4; // features per interaction kernel (compile time grows
-                                // faster than linearly with a function's size)
+constexpr int kIvRows = 256;          // rows per block of the interaction kernels (and of the
+                                      // pattern workspace's blocks)
+constexpr int kIvTableBufs = 2;       // table stages in LDS (copied one stage ahead)
+constexpr int kIvPatChunk = 16;       // units per pattern copy: 64 lanes x 16 bytes, 4 lanes per unit
+constexpr int kIvGatherBatch = 4;     // units whose table reads are issued together
+constexpr int kIvPerKernel = 4;       // features per interaction kernel (compile time grows
+                                      // faster than linearly with a function's size)
+
+// Resident blocks per CU and the LDS each takes, by the largest number of
+// partner accumulators among a kernel's features: three blocks (twelve waves)
+// while the registers fit 168 per lane (up to 128 accumulators), else two,
+// else one.  More resident blocks overlap one block's stores with another's
+// table reads better.
+struct IvShape {
+  int blocks_per_cu;
+  int table_bytes;  // one table buffer (the two stay below 64 KiB: 16-bit read offsets)
+  int ring;         // pattern chunks per wave (copied ring - 1 chunks ahead)
+  int pat_base() const { return kIvTableBufs * table_bytes; }
+  int lds_bytes() const { return pat_base() + kIvRows / 64 * ring * 1024; }
+};
+IvShape iv_shape(int max_partners) {
+  const IvShape s = max_partners <= 128 ? IvShape{3, 20480, 3}
+                    : max_partners <= 200 ? IvShape{2, 30720, 4}
+                                          : IvShape{1, 32768, 4};
+  return s;
+}
 
 std::string iv_kernel_name(int c) { return "wdf_iv_spec_" + std::to_string(c); }
 
+// Stages of the units [u0, u1): consecutive units whose tables fit one buffer.
+std::vector<std::pair<int, int>> iv_stages(const wdf_model *M, int u0, int u1, int table_bytes) {
+  std::vector<std::pair<int, int>> st;
+  for (int a = u0; a < u1;) {
+    int b = a;
+    int64_t tfl = 0;
+    while (b < u1) {
+      const int64_t t = tfl + ivunit_floats(M->iv_units[(size_t)b]);
+      if (b > a && 4 * t > table_bytes) break;
+      tfl = t;
+      ++b;
+    }
+    st.emplace_back(a, b);
+    a = b;
+  }
+  return st;
+}
+
+// Vector-memory instructions one wave issues, in order: `sure` of them
+// issued by every wave, `maybe` only by some (a stage copy's last, partial
+// chunk of pieces).  wait(e) emits the vmcnt wait after which copy e has
+// landed: at most the sure instructions issued after e may be outstanding.
+struct VmLog {
+  struct Ev {
+    int sure, maybe;
+  };
+  std::vector<Ev> ev;
+  int add(int sure, int maybe) {
+    ev.push_back({sure, maybe});
+    return (int)ev.size() - 1;
+  }
+  void wait(std::ostream &o, int e) const {
+    int after = 0;
+    for (size_t k = (size_t)e + 1; k < ev.size(); ++k) after += ev[k].sure;
+    after = std::min(after, 63);
+    // s_waitcnt fields (gfx9): vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8 (all ones: no wait)
+    const int imm = (after & 15) | ((after >> 4) << 14) | (7 << 4) | (15 << 8);
+    o << "  __builtin_amdgcn_sched_barrier(0);\n  __builtin_amdgcn_s_waitcnt(" << imm << ");  // vmcnt(" << after
+      << ")\n  __builtin_amdgcn_sched_barrier(0);\n";
+  }
+};
+
 std::string gen_iv(const wdf_model *M) {
   const int F = M->n_features;
+  constexpr int NW = kIvRows / 64;
   std::ostringstream o;
-  o << kPreamble << "typedef float vf4 __attribute__((ext_vector_type(4)));\n";
+  o << kPreamble << kStagePiece << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
+    << "typedef float vf2 __attribute__((ext_vector_type(2)));\n"
+    << "typedef const __attribute__((address_space(3))) unsigned char* lu8;\n"
+    << "typedef __attribute__((address_space(1))) float* gfp;  // a global address (stores stay global_store)\n"
+    // a workgroup barrier without __syncthreads' fence (which waits for every
+    // outstanding read, the prefetches included: the counted waits before the
+    // barrier cover what it must); the empty asm keeps memory accesses from
+    // moving across it
+    << "#define BARRIER() { __builtin_amdgcn_sched_barrier(0); asm volatile(\"\" ::: \"memory\"); "
+       "__builtin_amdgcn_s_barrier(); asm volatile(\"\" ::: \"memory\"); __builtin_amdgcn_sched_barrier(0); }\n"
+    // one wave's copy of its 64 rows of 16 units' patterns: lane L copies 16
+    // rows (L % 4) of unit L / 4, group g<L / 4> (a tree of selects on the
+    // bits of L / 4, not a chain of conditionals: those compile to branches)
+    << "#define PAT_CHUNK(dst";
+  for (int k = 0; k < kIvPatChunk; ++k) o << ", g" << k;
+  o << ") { ";
+  for (int k = 0; k < kIvPatChunk / 2; ++k)
+    o << "const u32 a" << k << "_ = pb0 ? (u32)(g" << 2 * k + 1 << ") : (u32)(g" << 2 * k << "); ";
+  for (int k = 0; k < kIvPatChunk / 4; ++k)
+    o << "const u32 b" << k << "_ = pb1 ? a" << 2 * k + 1 << "_ : a" << 2 * k << "_; ";
+  o << "const u32 c0_ = pb2 ? b1_ : b0_; const u32 c1_ = pb2 ? b3_ : b2_; const u32 g_ = pb3 ? c1_ : c0_; "
+    << "__builtin_amdgcn_global_load_lds((const void*)(pw + g_ * 256u), "
+       "(__attribute__((address_space(3))) void*)(dst), 16, 0, 0); }\n";
   static const char *C[4] = {"x", "y", "z", "w"};
+  // partner features of each feature
+  std::vector<std::vector<char>> partners((size_t)F, std::vector<char>((size_t)F, 0));
+  std::vector<int> npart((size_t)F, 0);
+  for (int i = 0; i < F; ++i) {
+    for (int k = M->iv_unit_off[(size_t)i]; k < M->iv_unit_off[(size_t)i + 1]; ++k)
+      for (int s = 0; s < M->iv_units[(size_t)k].cnt; ++s)
+        partners[(size_t)i][(size_t)M->iv_unit_partners[(size_t)k][(size_t)s]] = 1;
+    for (int j = 0; j < F; ++j) npart[(size_t)i] += partners[(size_t)i][(size_t)j];
+  }
   for (int c = 0; c * kIvPerKernel < F; ++c) {
-    o << "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void " << iv_kernel_name(c)
-      << "(const unsigned char* __restrict__ pat, i64 n, const float* __restrict__ t2, float* __restrict__ out, "
-         "i64 ldo, int live) {\n"
-      << "  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;\n"
-      << "  const i64 row = ((i64)blockIdx.x * 4 + wave) * 64 + lane;\n"
-      << "  const i64 rr = row < n ? row : n - 1;\n"
+    const int i0 = c * kIvPerKernel, i1 = std::min(F, (c + 1) * kIvPerKernel);
+    const IvShape sh = iv_shape(*std::max_element(npart.begin() + i0, npart.begin() + i1));
+    o << "extern \"C\" __global__ __launch_bounds__(" << kIvRows << ", " << sh.blocks_per_cu << ") void " << iv_kernel_name(c)
+      << "(const unsigned char* __restrict__ pat, i64 n, const float* __restrict__ tab, "
+         "float* __restrict__ out, i64 ldo, int live) {\n"
+      << "  __shared__ __attribute__((aligned(16))) float lds[" << sh.lds_bytes() / 4 << "];\n"
+      << "  const u32 lane = threadIdx.x & 63u;\n"
+      << "  const u32 wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);\n"
+      << "  const u32 wbase4 = wave * 256u;  // the wave's first table piece, in floats\n"
+      << "  const i64 row0 = (i64)blockIdx.x * " << kIvRows << ", row = row0 + threadIdx.x;\n"
+      << "  // the lane's share of its wave's pattern copies, and the wave's pattern ring\n"
+      << "  const u32 pu = lane >> 2;\n"
+      << "  const bool pb0 = (pu & 1u) != 0u, pb1 = (pu & 2u) != 0u, pb2 = (pu & 4u) != 0u, pb3 = (pu & 8u) != 0u;\n"
+      << "  const unsigned char* pw = pat + (i64)blockIdx.x * " << (int64_t)M->groups.size() * 256
+      << " + 64u * wave + 16u * (lane & 3u);\n"
+      << "  float* const ring = lds + " << sh.pat_base() / 4 << " + wave * " << sh.ring * 256 << "u;\n"
+      << "  const u32 pr = " << sh.pat_base() << "u + wave * " << sh.ring * 1024 << "u + lane;  // the lane's pattern bytes\n"
       << "  float* o = out + row;\n"
+      << "  float sink = 0.f;  // unused table components (zeros)\n"
       << "  switch (blockIdx.y) {\n";
-    for (int i = c * kIvPerKernel; i < std::min(F, (c + 1) * kIvPerKernel); ++i) {
+    for (int i = i0; i < i1; ++i) {
       const int u0 = M->iv_unit_off[(size_t)i], u1 = M->iv_unit_off[(size_t)i + 1];
-      std::vector<char> partner((size_t)F, 0);
-      for (int k = u0; k < u1; ++k)
-        for (int s = 0; s < M->iv_units[(size_t)k].cnt; ++s)
-          partner[(size_t)M->iv_unit_partners[(size_t)k][(size_t)s]] = 1;
+      const int U = u1 - u0, nchunks = (U + kIvPatChunk - 1) / kIvPatChunk;
+      const std::vector<char> &partner = partners[(size_t)i];
       o << "  case " << i - c * kIvPerKernel << ": {\n";
       for (int j = 0; j < F; ++j)
         if (partner[(size_t)j]) o << "    float a" << j << " = 0.f;\n";
-      // Units in batches of kIvBatch, one basic block each (`live` is always
-      // 1: the branches keep the scheduler from hoisting all of a case's loads
-      // to its top).  A batch's block loads the next batch's patterns (pn*)
-      // before its own table reads, which use the patterns loaded one block
-      // earlier (pc*).
-      auto load_patterns = [&](int k0, const char *dst) {
-        for (int k = k0; k < std::min(u1, k0 + kIvBatch); ++k)
-          o << "    " << dst << (k - k0) << " = pat[(i64)" << M->iv_units[(size_t)k].group << " * n + rr];\n";
+      const auto st = iv_stages(M, u0, u1, sh.table_bytes);
+      VmLog vm;
+      std::vector<int> tev(st.size(), -1), pev((size_t)nchunks, -1);
+      std::vector<char> pwaited((size_t)nchunks, 0);
+      auto tfloats = [&](int a, int b) {
+        return M->iv_units[(size_t)b - 1].dst + ivunit_floats(M->iv_units[(size_t)b - 1]) - M->iv_units[(size_t)a].dst;
       };
-      if (u0 < u1) {
-        o << "    u32 pc0";
-        for (int b = 1; b < kIvBatch; ++b) o << ", pc" << b;
-        for (int b = 0; b < kIvBatch; ++b) o << ", pn" << b;
-        o << ";\n";
-        load_patterns(u0, "pc");
+      auto copy_tables = [&](size_t s) {
+        const int a = st[s].first, b = st[s].second;
+        const int64_t n16 = tfloats(a, b) / 4;
+        emit_stage_copy(o, M->iv_units[(size_t)a].dst, (int64_t)(s % kIvTableBufs) * sh.table_bytes / 4, n16, kIvRows);
+        tev[s] = vm.add((int)(n16 / kIvRows), n16 % kIvRows ? 1 : 0);
+      };
+      auto copy_patterns = [&](int ch) {
+        o << "  PAT_CHUNK(ring + " << (ch % sh.ring) * 256;
+        for (int k = 0; k < kIvPatChunk; ++k)
+          o << ", " << M->iv_units[(size_t)std::min(u1 - 1, u0 + ch * kIvPatChunk + k)].group;
+        o << ")\n";
+        pev[(size_t)ch] = vm.add(1, 0);
+      };
+      // prologue: the first table stages, the first pattern chunks
+      for (size_t s = 0; s + 1 < (size_t)kIvTableBufs && s < st.size(); ++s) copy_tables(s);
+      int next_chunk = 0;
+      for (; next_chunk < std::min(nchunks, sh.ring); ++next_chunk) copy_patterns(next_chunk);
+      if (!st.empty()) {
+        vm.wait(o, tev[0]);
+        o << "  BARRIER();\n";
       }
-      for (int k0 = u0; k0 < u1; k0 += kIvBatch) {
-        o << "    if (live) {\n";
-        if (k0 + kIvBatch < u1) load_patterns(k0 + kIvBatch, "pn");
-        for (int k = k0; k < std::min(u1, k0 + kIvBatch); ++k) {
-          const IvUnit &u = M->iv_units[(size_t)k];
-          const int64_t E = (int64_t)1 << u.depth;
-          o << "    { const vf4* t = (const vf4*)(t2 + " << u.dst << ") + pc" << (k - k0) << ";";
-          for (int pl = 0; 4 * pl < u.cnt; ++pl) {
-            o << " { const vf4 v = t[" << pl * E << "];";
-            for (int cc = 0; cc < 4 && 4 * pl + cc < u.cnt; ++cc)
-              o << " a" << M->iv_unit_partners[(size_t)k][(size_t)(4 * pl + cc)] << " += v." << C[cc] << ";";
-            o << " }";
+      for (size_t s = 0; s < st.size(); ++s) {
+        const int buf = (int)(s % kIvTableBufs);
+        if (s + kIvTableBufs - 1 < st.size()) copy_tables(s + kIvTableBufs - 1);
+        const int a = st[s].first, b = st[s].second;
+        const int64_t sbase = M->iv_units[(size_t)a].dst;
+        o << "  {\n";
+        auto read_patterns = [&](int k0) {
+          for (int k = k0; k < std::min(b, k0 + kIvGatherBatch); ++k) {
+            const int t = k - u0, ch = t / kIvPatChunk;
+            if (!pwaited[(size_t)ch]) {
+              vm.wait(o, pev[(size_t)ch]);
+              pwaited[(size_t)ch] = 1;
+            }
+            o << "  const u32 q" << k - a << " = ((lu8)lds)[pr + " << (ch % sh.ring) * 1024 + (t % kIvPatChunk) * 64
+              << "u];\n";
           }
-          o << " }\n";
+        };
+        // batches of kIvGatherBatch units: the table reads of a batch are
+        // issued together, then a scheduling barrier, then their adds (left to
+        // itself the compiler reads, waits and adds one unit at a time)
+        std::vector<char> touched((size_t)F, 0);
+        std::map<int, std::string> adds_of;  // first unit of a batch -> its adds
+        auto gathers = [&](int k0) {
+          std::ostringstream adds;
+          for (int k = k0; k < std::min(b, k0 + kIvGatherBatch); ++k) {
+            const IvUnit &u = M->iv_units[(size_t)k];
+            const int64_t E = (int64_t)1 << u.depth;
+            const int64_t ofs = (int64_t)buf * sh.table_bytes / 4 + (u.dst - sbase);  // floats
+            const int nq = ivunit_quads(u.cnt), w = ivunit_tail(u.cnt);
+            const std::string q = "q" + std::to_string(k - a);
+            auto add = [&](const std::string &v, int col) {
+              if (col < u.cnt) {
+                const int j = M->iv_unit_partners[(size_t)k][(size_t)col];
+                touched[(size_t)j] = 1;
+                adds << " a" << j << " += " << v << ";";
+              } else {
+                adds << " sink += " << v << ";";
+              }
+            };
+            for (int pl = 0; pl < nq; ++pl) {
+              const std::string g = "g" + std::to_string(k - a) + "_" + std::to_string(pl);
+              o << "  const vf4 " << g << " = ((const vf4*)(lds + " << ofs + 4 * E * pl << "))[" << q << "];\n";
+              for (int cc = 0; cc < 4; ++cc) add(g + "." + C[cc], 4 * pl + cc);
+            }
+            const std::string g = "h" + std::to_string(k - a);
+            if (w == 2) {
+              o << "  const vf2 " << g << " = ((const vf2*)(lds + " << ofs + 4 * E * nq << "))[" << q << "];\n";
+              add(g + ".x", 4 * nq);
+              add(g + ".y", 4 * nq + 1);
+            } else if (w == 1) {
+              o << "  const float " << g << " = (lds + " << ofs + 4 * E * nq << ")[" << q << "];\n";
+              add(g, 4 * nq);
+            }
+            adds << "\n";
+          }
+          adds_of[k0] = adds.str();
+        };
+        constexpr int B = kIvGatherBatch;
+        read_patterns(a);
+        for (int k0 = a; k0 < b; k0 += B) {
+          const int k1 = std::min(b, k0 + B);
+          // the next batch's pattern reads, then this batch's table reads
+          if (k1 < b) read_patterns(k1);
+          gathers(k0);
+          o << "  __builtin_amdgcn_sched_barrier(0);\n" << adds_of[k0] << "  __builtin_amdgcn_sched_barrier(0);\n";
+          // the adds waited for this batch's table reads, and so for the
+          // pattern reads of its units (issued before them): a chunk whose
+          // units are all read frees its ring slot for the chunk sh.ring on
+          while (next_chunk < nchunks && (next_chunk - sh.ring + 1) * kIvPatChunk <= k1 - u0) copy_patterns(next_chunk++);
         }
-        if (k0 + kIvBatch < u1)
-          for (int b = 0; b < std::min(kIvBatch, u1 - k0 - kIvBatch); ++b) o << "    pc" << b << " = pn" << b << ";\n";
-        o << "    }\n";
+        // keep each stage's accumulations inside the stage
+        for (int j = 0; j < F; ++j)
+          if (touched[(size_t)j]) o << "  asm volatile(\"\" : \"+v\"(a" << j << "));\n";
+        o << "  }\n";
+        if (s + 1 < st.size()) {
+          vm.wait(o, tev[s + 1]);
+          o << "  BARRIER();\n";
+        }
       }
-      o << "    if (row < n) {\n";
-      for (int j = 0; j < F; ++j)
-        o << "      o[(i64)" << (int64_t)i * F + j << " * ldo] = "
-          << (partner[(size_t)j] ? "a" + std::to_string(j) : std::string("0.f")) << ";\n";
+      // non-temporal stores: the F x F values per row stream to HBM without
+      // taking the caches the table and pattern copies read through.  The
+      // address steps by ldo from store to store (opaque to the compiler,
+      // which otherwise forms every (i F + j) ldo product and spills them)
+      o << "    if (row < n) {\n      gfp p = (gfp)(o + (i64)" << (int64_t)i * F << " * ldo);\n";
+      for (int j = 0; j < F; ++j) {
+        o << "      __builtin_nontemporal_store(" << (partner[(size_t)j] ? "a" + std::to_string(j) : std::string("0.f"))
+          << ", p);";
+        if (j + 1 < F) o << " p += ldo; asm volatile(\"\" : \"+v\"(p));";
+        o << "\n";
+      }
       o << "    }\n  } break;\n";
     }
-    o << "  default: break;\n  }\n}\n";
+    o << "  default: break;\n  }\n"
+      << "  if (live == 2) o[0] = sink;  // never (live is 1): keeps the sink's reads whole\n}\n";
   }
   return o.str();
 }
 
-// Patterns of every group for every row (Def. Decision Pattern: bit 1 = the
-// row follows the group's path, root bit first), one byte per (group, row)
-// into pat[g * n + row]: one thread per row, the row's threshold ranks in
-// registers, the node tests of all trees in straight-line code (raw splits,
-// turned into path bits by the group's right turns), one store per group.
+// Patterns of every group for every row (Def. Decision Pattern), as raw
+// splits (bit 1: the row went left, root bit first; the interaction tables
+// apply the group's right turns) stored at their table slot r ^ (r >> 3) ^
+// (r >> 6): one byte per (group, row), in blocks of 256 rows, all groups of
+// a block together: pat[(row / 256) G 256 + g 256 + row % 256], for every row
+// below ldp (a multiple of 512; rows from n on repeat row n - 1).  The
+// interaction kernels copy whole 16-byte pieces, and one block's pieces come
+// from one span of G x 256 bytes rather than from G rows of the workspace.
+// One thread per row, the row's threshold ranks in registers, the node tests
+// of all trees in straight-line code, one store per group.
 constexpr int64_t kPatLdsThresholds = 16384;  // thresholds staged in LDS up to 64 KB
 
 std::string gen_patterns(const wdf_model *M, const TreeIndex &ix) {
@@ -1130,21 +1339,25 @@ std::string gen_patterns(const wdf_model *M, const TreeIndex &ix) {
   std::vector<char> used((size_t)F, 0);
   for (const PathNode &pn : M->path) used[(size_t)pn.feat] = 1;
   o << "extern \"C\" __global__ __launch_bounds__(256) void wdf_patterns_spec(const float* __restrict__ X, i64 ldx, "
-       "const float* __restrict__ thr, unsigned char* __restrict__ pat, i64 n, int live) {\n"
+       "const float* __restrict__ thr, unsigned char* __restrict__ pat, i64 n, i64 ldp, int live) {\n"
     << "  const u32 zero = 0u;\n"
     << "  const i64 row = (i64)blockIdx.x * 256 + threadIdx.x;\n"
-    << "  const i64 rr = row < n ? row : n - 1;\n";
+    << "  const i64 rr = row < n ? row : n - 1;\n"
+    << "  unsigned char* const pb = pat + (i64)blockIdx.x * " << (int64_t)M->groups.size() * 256 << " + threadIdx.x;\n";
   if (lds)
     o << "  extern __shared__ float lthr[];\n"
       << "  for (int i = threadIdx.x; i < " << P.thr_pad.size() << "; i += 256) lthr[i] = thr[i];\n"
       << "  __syncthreads();\n";
   emit_rank_words(o, M, used, lds);
+  // the grid covers exactly ldp rows (the test, always true, keeps each
+  // store in a block of its own: one straight-line block of all trees lets
+  // the scheduler interleave them at a high register cost); the slot is
+  // computed from the pattern itself (the ancestors' registers would stay
+  // live across the trees)
   gen.on_group = [&](int64_t g, const std::string &p) {
-    const Group &gr = M->groups[(size_t)g];
-    uint32_t mask = 0;
-    for (int k = 0; k < gr.depth; ++k)
-      if (M->path[(size_t)gr.path_off + k].dir) mask |= 1u << (gr.depth - 1 - k);
-    o << "if (row < n) pat[(i64)" << g << " * n + row] = (unsigned char)(" << p << " ^ " << mask << "u);\n";
+    const int d = M->groups[(size_t)g].depth;
+    o << "if (row < ldp) pb[" << g * 256 << "] = (unsigned char)("
+      << (d > 6 ? p + " ^ (" + p + " >> 3) ^ (" + p + " >> 6)" : d > 3 ? p + " ^ (" + p + " >> 3)" : p) << ");\n";
   };
   if (!M->groups.empty()) gen.range(0, (int64_t)M->groups.size());
   o << "}\n";
@@ -1200,24 +1413,27 @@ int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, 
   if (!M->jit || M->jit->iv.empty() || !M->jit->patterns)
     return set_error(WDF_E_INVALID_ARG, "specialised interaction kernel missing");
   if (n <= 0) return WDF_OK;
+  if ((uintptr_t)pat % 16) return set_error(WDF_E_INVALID_ARG, "interaction workspace not 16-byte aligned");
+  int64_t ldp = iv_pattern_stride(n);
   {
     const JitPlan &P = M->jp;
     const float *thr = P.d_thr_pad.as<float>();
     int live = 1;
-    void *pargs[] = {(void *)&X, &ldx, (void *)&thr, &pat, &n, &live};
+    void *pargs[] = {(void *)&X, &ldx, (void *)&thr, &pat, &n, &ldp, &live};
     const size_t lds = (int64_t)P.thr_pad.size() <= kPatLdsThresholds ? P.thr_pad.size() * sizeof(float) : 0;
-    hipError_t e = hipModuleLaunchKernel(M->jit->patterns, (unsigned)((n + 255) / 256), 1, 1, 256, 1, 1,
-                                         (unsigned)lds, s, pargs, nullptr);
+    hipError_t e = hipModuleLaunchKernel(M->jit->patterns, (unsigned)(ldp / 256), 1, 1, 256, 1, 1, (unsigned)lds, s,
+                                         pargs, nullptr);
     if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(patterns)");
   }
   const float *t2 = bg->d_xtab.as<float>();
   int live = 1;
   void *args[] = {(void *)&pat, &n, (void *)&t2, &iv, &ldiv, &live};
-  const unsigned blocks = (unsigned)((n + 255) / 256);
+  const unsigned blocks = (unsigned)((n + kIvRows - 1) / kIvRows);
   const int F = M->n_features;
   for (int c = 0; c < (int)M->jit->iv.size(); ++c) {
     const unsigned fc = (unsigned)std::min(kIvPerKernel, F - c * kIvPerKernel);
-    hipError_t e = hipModuleLaunchKernel(M->jit->iv[(size_t)c], blocks, fc, 1, 256, 1, 1, 0, s, args, nullptr);
+    hipError_t e =
+        hipModuleLaunchKernel(M->jit->iv[(size_t)c], blocks, fc, 1, kIvRows, 1, 1, 0, s, args, nullptr);
     if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(interaction)");
   }
   return WDF_OK;

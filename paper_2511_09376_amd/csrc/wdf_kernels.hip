@@ -502,17 +502,25 @@ __global__ __launch_bounds__(256) void k_expand_iv(const Group *__restrict__ gro
   }
 }
 
-// Interleaved interaction tables (IvUnit): entry [plane][p][c] of a unit is
-// the pair table of (i, partner 4 plane + c) at pattern p, 0 past the last
-// partner.
+// Interleaved interaction tables (IvUnit): value column k of a unit (its
+// partner k, 0 past the last partner) at raw index r is the pair table of
+// (i, partner k) at pattern r ^ mask, stored at slot ivunit_slot(r) of the
+// column's plane; the rounding pad after the last plane is zeroed.
 __global__ __launch_bounds__(256) void k_ivtab(const IvUnit *__restrict__ units, const float *__restrict__ tab,
                                                float *__restrict__ t2) {
   const IvUnit u = units[blockIdx.x];
   const int d = u.depth, E = 1 << d;
-  const int total = 4 * ((u.cnt + 3) / 4) * E;
+  const int nq = ivunit_quads(u.cnt), w = ivunit_tail(u.cnt);
+  const int cols = 4 * nq + w, total = (int)ivunit_floats(u);
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int c = idx & 3, p = (idx >> 2) & (E - 1), s = (idx >> (d + 2)) * 4 + c;
-    t2[u.dst + idx] = s < u.cnt ? tab[u.src + ((int64_t)u.q[s] << d) + p] : 0.f;
+    if (idx >= cols * E) {
+      t2[u.dst + idx] = 0.f;
+      continue;
+    }
+    const int k = idx >> d, r = idx & (E - 1);
+    const int s = (int)ivunit_slot((uint32_t)r);
+    const int64_t at = k < 4 * nq ? (int64_t)(k >> 2) * 4 * E + 4 * s + (k & 3) : (int64_t)4 * nq * E + w * s + (k - 4 * nq);
+    t2[u.dst + at] = k < u.cnt ? tab[u.src + ((int64_t)u.q[k] << d) + (r ^ (int)u.mask)] : 0.f;
   }
 }
 

@@ -111,18 +111,36 @@ def _path_feature_sets(ens):
 def test_iv_source_matches_the_layout(wdf, which):
     """The specialised interaction kernels add one pair value per (group,
     feature i at its first occurrence, partner j), i.e. sum over groups of
-    d'(d' - 1) adds; one kernel per four features; every output iv[i][j] is
-    written once per row, the diagonal as 0."""
+    d'(d' - 1) adds, from one 16-byte read per four partners and one 4- or
+    8-byte read for a last one or two; one kernel per four features; every
+    output iv[i][j] is written once per row, the diagonal as 0; the pattern
+    kernel stores every group's raw splits at their table slot."""
     ens = synth.WORKLOADS["small"].ensemble() if which == "small" else _edge()
     F = ens.n_features
     src = wdf.iv_source(ens)
     sets = _path_feature_sets(ens)
-    assert len(re.findall(r"\+= v\.", src)) == sum(len(s) * (len(s) - 1) for s in sets)
+    assert len(re.findall(r"\ba\d+ \+= [gh]\d+", src)) == sum(len(s) * (len(s) - 1) for s in sets)
+    # reads: per (group, first position) with c = d' - 1 partners, c // 4
+    # 16-byte reads (one more for c % 4 == 3), and one narrow read for c % 4 in (1, 2)
+    wide = sum(len(s) * ((len(s) - 1) // 4 + ((len(s) - 1) % 4 == 3)) for s in sets if len(s) > 1)
+    narrow = sum(len(s) * ((len(s) - 1) % 4 in (1, 2)) for s in sets if len(s) > 1)
+    assert len(re.findall(r"const vf4 g\d+_\d+ = ", src)) == wide
+    assert len(re.findall(r"const (?:vf2|float) h\d+ = ", src)) == narrow
     assert len(re.findall(r"void wdf_iv_spec_\d+\(", src)) == (F + 3) // 4
-    # the pattern kernel stores every group's pattern, XOR-ed with its right turns
     assert "void wdf_patterns_spec(" in src
-    assert len(re.findall(r"pat\[\(i64\)\d+ \* n \+ row\] = ", src)) == len(sets)
-    writes = re.findall(r"o\[\(i64\)(\d+) \* ldo\] = (\S+);", src)
+    # one store per group with a path (a single-leaf tree has no pattern),
+    # each at its group's 256-byte piece of the row block
+    stores = [int(g) for g in re.findall(r"if \(row < ldp\) pb\[(\d+)\] = ", src)]
+    assert len(stores) == len(set(stores)) == len(sets)
+    assert all(s % 256 == 0 for s in stores)
+    # each case stores row i of the matrix: from o + i F ldo, one store per j,
+    # the address stepping by ldo
+    writes = []
+    for blk in src.split("gfp p = (gfp)(o + (i64)")[1:]:
+        base = int(blk[:blk.index(" ")])
+        vals = re.findall(r"__builtin_nontemporal_store\((\S+), p\);", blk[:blk.index("} break;")])
+        assert blk.count("p += ldo;") == len(vals) - 1
+        writes += [(base + j, v) for j, v in enumerate(vals)]
     assert sorted(int(k) for k, _ in writes) == list(range(F * F))
     for k, v in writes:
         i, j = divmod(int(k), F)

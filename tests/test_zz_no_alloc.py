@@ -41,7 +41,7 @@ def test_noalloc_equals_workspace_entry(wdf, workload, kname):
     assert bg.specialised == (kname == "specialised")
     F = ens.n_features
     G = model.groups()["depth"].size
-    n_max = wdf.NOALLOC_SCRATCH_BYTES // G
+    n_max = wdf.NOALLOC_SCRATCH_BYTES // G // 512 * 512  # rows of the pattern workspace come in blocks of 512
     n1 = min(n_max, 12000)
     X = w.consumers(n1 + 4000)
     print(f"[no-alloc] {workload} {kname}: {G} groups, at most {n_max} rows per call", flush=True)
