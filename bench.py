@@ -91,6 +91,25 @@ def measured_traffic(wdf, ens, workload, gather):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def measured_iv_traffic(wdf, ens, workload):
+    """HBM bytes per step of the interaction kernels (pattern and interaction
+    launches) from the committed counter summary, while the generated source
+    is the one the counters were taken on; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"iv_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha1(wdf.iv_source(ens).encode()).hexdigest()
+    if fields.get("source_sha1") != sha or "traffic_bytes_per_step" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_step"])
+
+
 def cpu_model_name() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -387,8 +406,10 @@ def main():
         # the interaction launches write F * F floats per row: HBM-bound by that output
         out_bytes = 4.0 * ens.n_features ** 2 * n
         achieved = out_bytes / (explain_ms * 1e-3)
+        # (the counters were taken with the default chunk of rows per launch)
+        traffic = measured_iv_traffic(wdf, ens, args.workload) if bg.specialised and args.iv_chunk == 1 << 18 else None
         roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK, "traffic": None,
+                    "frac": achieved / HBM_PEAK, "traffic": traffic,
                     "kernel": ("wdf_patterns_spec + wdf_iv_spec_*" if bg.specialised else "k_patterns_u8 + k_explain_iv"),
                     "kernel_ms": explain_ms, "bytes_per_row": 4 * ens.n_features ** 2}
     else:

@@ -14,6 +14,7 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -42,7 +43,8 @@ struct JitPart {
 };
 
 struct JitModule {
-  std::shared_ptr<JitPart> hist_part, explain_part, iv_part;
+  std::shared_ptr<JitPart> hist_part, explain_part;
+  std::vector<std::shared_ptr<JitPart>> iv_parts;  // programs of the interaction and pattern kernels
   hipFunction_t hist = nullptr, explain = nullptr;
   std::vector<hipFunction_t> iv;  // interaction kernels, features [c * 4, c * 4 + 4)
   hipFunction_t patterns = nullptr;  // all groups' patterns of consumer rows, for the interaction kernels
@@ -953,11 +955,18 @@ int jit_compile_all(wdf_model *M, const std::vector<std::pair<std::string, std::
   std::vector<std::vector<char>> code(todo.size());
   std::vector<int> rcs(todo.size(), WDF_OK);
   std::vector<std::string> errs(todo.size());
+  // at most as many compile threads as the host has cores (each hipRTC
+  // compile holds its own copy of the compiler's state)
+  const size_t nthreads =
+      std::min<size_t>(todo.size(), std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency())));
+  std::atomic<size_t> next{0};
   std::vector<std::thread> th;
-  for (size_t k = 0; k < todo.size(); ++k)
-    th.emplace_back([&, k] {
-      rcs[k] = compile(progs[todo[k]].first, code[k]);
-      if (rcs[k]) errs[k] = wdf_last_error();  // the error text is thread-local
+  for (size_t t = 0; t < nthreads; ++t)
+    th.emplace_back([&] {
+      for (size_t k; (k = next.fetch_add(1)) < todo.size();) {
+        rcs[k] = compile(progs[todo[k]].first, code[k]);
+        if (rcs[k]) errs[k] = wdf_last_error();  // the error text is thread-local
+      }
     });
   for (auto &t : th) t.join();
   for (size_t k = 0; k < todo.size(); ++k)
@@ -1063,6 +1072,7 @@ constexpr int kIvPatChunk = 16;       // units per pattern copy: 64 lanes x 16 b
 constexpr int kIvGatherBatch = 4;     // units whose table reads are issued together
 constexpr int kIvPerKernel = 4;       // features per interaction kernel (compile time grows
                                       // faster than linearly with a function's size)
+constexpr int kIvKernelsPerProgram = 4;  // kernels per hipRTC program (programs compile in parallel)
 
 // Resident blocks per CU and the LDS each takes, by the largest number of
 // partner accumulators among a kernel's features: three blocks (twelve waves)
@@ -1076,10 +1086,14 @@ struct IvShape {
   int pat_base() const { return kIvTableBufs * table_bytes; }
   int lds_bytes() const { return pat_base() + kIvRows / 64 * ring * 1024; }
 };
+const IvShape kIvShapes[3] = {{3, 20480, 3}, {2, 30720, 4}, {1, 32768, 4}};
 IvShape iv_shape(int max_partners) {
-  const IvShape s = max_partners <= 128 ? IvShape{3, 20480, 3}
-                    : max_partners <= 200 ? IvShape{2, 30720, 4}
-                                          : IvShape{1, 32768, 4};
+  return kIvShapes[max_partners <= 128 ? 0 : max_partners <= 200 ? 1 : 2];
+}
+// the next shape with fewer resident blocks (for a kernel that spilled), or itself
+IvShape iv_shape_fewer(const IvShape &s) {
+  for (int k = 0; k < 2; ++k)
+    if (kIvShapes[k].blocks_per_cu == s.blocks_per_cu) return kIvShapes[k + 1];
   return s;
 }
 
@@ -1127,14 +1141,38 @@ struct VmLog {
   }
 };
 
-std::string gen_iv(const wdf_model *M) {
-  const int F = M->n_features;
-  constexpr int NW = kIvRows / 64;
+// the partner features of each feature (units' partners), and their counts
+struct IvPartners {
+  std::vector<std::vector<char>> of;
+  std::vector<int> count;
+  explicit IvPartners(const wdf_model *M) {
+    const int F = M->n_features;
+    of.assign((size_t)F, std::vector<char>((size_t)F, 0));
+    count.assign((size_t)F, 0);
+    for (int i = 0; i < F; ++i) {
+      for (int k = M->iv_unit_off[(size_t)i]; k < M->iv_unit_off[(size_t)i + 1]; ++k)
+        for (int s = 0; s < M->iv_units[(size_t)k].cnt; ++s)
+          of[(size_t)i][(size_t)M->iv_unit_partners[(size_t)k][(size_t)s]] = 1;
+      for (int j = 0; j < F; ++j) count[(size_t)i] += of[(size_t)i][(size_t)j];
+    }
+  }
+  IvShape shape(int c, int F) const {
+    const int i0 = c * kIvPerKernel, i1 = std::min(F, (c + 1) * kIvPerKernel);
+    return iv_shape(*std::max_element(count.begin() + i0, count.begin() + i1));
+  }
+};
+
+int iv_kernel_count(const wdf_model *M) { return (M->n_features + kIvPerKernel - 1) / kIvPerKernel; }
+
+// types and macros of the interaction kernels
+std::string gen_iv_preamble() {
   std::ostringstream o;
   o << kPreamble << kStagePiece << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
     << "typedef float vf2 __attribute__((ext_vector_type(2)));\n"
     << "typedef const __attribute__((address_space(3))) unsigned char* lu8;\n"
     << "typedef __attribute__((address_space(1))) float* gfp;  // a global address (stores stay global_store)\n"
+    // (stores of iv are non-temporal: the F x F values per row stream to HBM
+    // without taking the caches the table and pattern copies read through)
     // a workgroup barrier without __syncthreads' fence (which waits for every
     // outstanding read, the prefetches included: the counted waits before the
     // barrier cover what it must); the empty asm keeps memory accesses from
@@ -1154,19 +1192,17 @@ std::string gen_iv(const wdf_model *M) {
   o << "const u32 c0_ = pb2 ? b1_ : b0_; const u32 c1_ = pb2 ? b3_ : b2_; const u32 g_ = pb3 ? c1_ : c0_; "
     << "__builtin_amdgcn_global_load_lds((const void*)(pw + g_ * 256u), "
        "(__attribute__((address_space(3))) void*)(dst), 16, 0, 0); }\n";
+  return o.str();
+}
+
+// interaction kernel c (features [4c, 4c + 4)) with resident-block shape sh
+std::string gen_iv_kernel(const wdf_model *M, const IvPartners &P, int c, const IvShape &sh) {
+  const int F = M->n_features;
+  constexpr int NW = kIvRows / 64;
+  std::ostringstream o;
   static const char *C[4] = {"x", "y", "z", "w"};
-  // partner features of each feature
-  std::vector<std::vector<char>> partners((size_t)F, std::vector<char>((size_t)F, 0));
-  std::vector<int> npart((size_t)F, 0);
-  for (int i = 0; i < F; ++i) {
-    for (int k = M->iv_unit_off[(size_t)i]; k < M->iv_unit_off[(size_t)i + 1]; ++k)
-      for (int s = 0; s < M->iv_units[(size_t)k].cnt; ++s)
-        partners[(size_t)i][(size_t)M->iv_unit_partners[(size_t)k][(size_t)s]] = 1;
-    for (int j = 0; j < F; ++j) npart[(size_t)i] += partners[(size_t)i][(size_t)j];
-  }
-  for (int c = 0; c * kIvPerKernel < F; ++c) {
+  {
     const int i0 = c * kIvPerKernel, i1 = std::min(F, (c + 1) * kIvPerKernel);
-    const IvShape sh = iv_shape(*std::max_element(npart.begin() + i0, npart.begin() + i1));
     o << "extern \"C\" __global__ __launch_bounds__(" << kIvRows << ", " << sh.blocks_per_cu << ") void " << iv_kernel_name(c)
       << "(const unsigned char* __restrict__ pat, i64 n, const float* __restrict__ tab, "
          "float* __restrict__ out, i64 ldo, int live) {\n"
@@ -1188,7 +1224,7 @@ std::string gen_iv(const wdf_model *M) {
     for (int i = i0; i < i1; ++i) {
       const int u0 = M->iv_unit_off[(size_t)i], u1 = M->iv_unit_off[(size_t)i + 1];
       const int U = u1 - u0, nchunks = (U + kIvPatChunk - 1) / kIvPatChunk;
-      const std::vector<char> &partner = partners[(size_t)i];
+      const std::vector<char> &partner = P.of[(size_t)i];
       o << "  case " << i - c * kIvPerKernel << ": {\n";
       for (int j = 0; j < F; ++j)
         if (partner[(size_t)j]) o << "    float a" << j << " = 0.f;\n";
@@ -1299,11 +1335,13 @@ std::string gen_iv(const wdf_model *M) {
           o << "  BARRIER();\n";
         }
       }
-      // non-temporal stores: the F x F values per row stream to HBM without
-      // taking the caches the table and pattern copies read through.  The
-      // address steps by ldo from store to store (opaque to the compiler,
-      // which otherwise forms every (i F + j) ldo product and spills them)
-      o << "    if (row < n) {\n      gfp p = (gfp)(o + (i64)" << (int64_t)i * F << " * ldo);\n";
+      // the row's iv[i][j] for every j, after all reads: the stores count in
+      // the same in-order counter (vmcnt) as the copies into LDS, so a store
+      // issued earlier would hold up every later counted wait until HBM
+      // acknowledged it.  The address steps by ldo from store to store (opaque
+      // to the compiler, which otherwise forms every (i F + j) ldo product and
+      // spills them)
+      o << "    if (row < n) {\n      gfp p = (gfp)o + (i64)" << (int64_t)i * F << " * ldo;\n";
       for (int j = 0; j < F; ++j) {
         o << "      __builtin_nontemporal_store(" << (partner[(size_t)j] ? "a" + std::to_string(j) : std::string("0.f"))
           << ", p);";
@@ -1316,6 +1354,14 @@ std::string gen_iv(const wdf_model *M) {
       << "  if (live == 2) o[0] = sink;  // never (live is 1): keeps the sink's reads whole\n}\n";
   }
   return o.str();
+}
+
+// all interaction kernels, each with the shape its partner count gives
+std::string gen_iv(const wdf_model *M) {
+  const IvPartners P(M);
+  std::string src = gen_iv_preamble();
+  for (int c = 0; c < iv_kernel_count(M); ++c) src += gen_iv_kernel(M, P, c, P.shape(c, M->n_features));
+  return src;
 }
 
 // Patterns of every group for every row (Def. Decision Pattern), as raw
@@ -1383,27 +1429,45 @@ int jit_build_iv(wdf_model *M) {
   if (M->iv_units.empty() || iv_spec_ops(M) > kMaxIvSpecOps)
     return set_error(WDF_E_UNSUPPORTED, "specialised interaction kernel: %lld table loads and adds exceed %lld",
                      (long long)iv_spec_ops(M), (long long)kMaxIvSpecOps);
-  const std::string src = gen_iv(M) + gen_patterns(M, index_tree_groups(M));
-  std::shared_ptr<JitPart> part = cached_part(M, src);
-  if (!part) {
-    std::vector<char> code;
-    int rc = compile(src, code);
+  // programs of kIvKernelsPerProgram kernels each, and the pattern kernel,
+  // compiled in parallel; a kernel that spills registers at its shape is
+  // generated again with fewer resident blocks (more registers per lane)
+  const IvPartners P(M);
+  const int nk = iv_kernel_count(M);
+  std::vector<IvShape> shapes;
+  for (int c = 0; c < nk; ++c) shapes.push_back(P.shape(c, M->n_features));
+  const std::string pre = gen_iv_preamble();
+  const std::string pat_src = std::string(kPreamble) + gen_patterns(M, index_tree_groups(M));
+  std::vector<hipFunction_t> fns((size_t)nk, nullptr);
+  std::vector<std::shared_ptr<JitPart>> parts;
+  for (int attempt = 0;; ++attempt) {
+    std::vector<std::pair<std::string, std::string>> progs;
+    for (int c0 = 0; c0 < nk; c0 += kIvKernelsPerProgram) {
+      std::string src = pre;
+      for (int c = c0; c < std::min(nk, c0 + kIvKernelsPerProgram); ++c) src += gen_iv_kernel(M, P, c, shapes[(size_t)c]);
+      progs.push_back({src, iv_kernel_name(c0)});
+    }
+    progs.push_back({pat_src, "wdf_patterns_spec"});
+    int rc = jit_compile_all(M, progs);
     if (rc) return rc;
-    if ((rc = load_part(M, src, code, iv_kernel_name(0).c_str(), part))) return rc;
+    parts.clear();
+    for (const auto &pr : progs) parts.push_back(cached_part(M, pr.first));
+    bool again = false;
+    for (int c = 0; c < nk; ++c) {
+      hipError_t e = hipModuleGetFunction(&fns[(size_t)c], parts[(size_t)(c / kIvKernelsPerProgram)]->mod,
+                                          iv_kernel_name(c).c_str());
+      if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(interaction)");
+      const IvShape fewer = iv_shape_fewer(shapes[(size_t)c]);
+      if (attempt < 2 && spill_bytes(fns[(size_t)c]) > 0 && fewer.blocks_per_cu < shapes[(size_t)c].blocks_per_cu) {
+        shapes[(size_t)c] = fewer;
+        again = true;
+      }
+    }
+    if (!again) break;
   }
-  std::vector<hipFunction_t> fns;
-  for (int c = 0; c * kIvPerKernel < M->n_features; ++c) {
-    hipFunction_t f = nullptr;
-    hipError_t e = hipModuleGetFunction(&f, part->mod, iv_kernel_name(c).c_str());
-    if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(interaction)");
-    fns.push_back(f);
-  }
-  hipFunction_t pf = nullptr;
-  hipError_t e = hipModuleGetFunction(&pf, part->mod, "wdf_patterns_spec");
-  if (e != hipSuccess) return hip_error(e, "hipModuleGetFunction(patterns)");
-  M->jit->iv_part = part;
+  M->jit->iv_parts = parts;
   M->jit->iv = fns;
-  M->jit->patterns = pf;
+  M->jit->patterns = parts.back()->fn;
   return WDF_OK;
 }
 

@@ -1,6 +1,7 @@
 """CPU checks of the benchmark's host logic: the method-op count behind the
 roofline figure, and the refusal of more than one GPU."""
 import os
+import re
 import subprocess
 import sys
 
@@ -101,3 +102,23 @@ def test_traffic_summary_matches_the_current_explain_kernel(bench):
     # phi written: 2 x 127 x 4 B per row over 3M rows, 3.05 GB): within 1.5x
     algorithmic = 2 * 127 * 4 * 3_000_000
     assert algorithmic <= traffic <= 1.5 * algorithmic
+
+
+def test_traffic_summary_matches_the_current_interaction_kernels(bench):
+    """The same for the interaction kernels: the committed summary was taken
+    on the pattern and interaction kernels the generator writes today, and the
+    measured bytes per step lie between the output alone (F x F floats per
+    row) and the output plus one pattern byte per unit and row read and one
+    per group and row written, with 10 % to spare."""
+    from paper_2511_09376_amd import wdf
+    if not os.path.exists(wdf.LIB_PATH):
+        pytest.skip("libwdf.so not built")
+    ens = synth.WORKLOADS["paper"].ensemble()
+    traffic = bench.measured_iv_traffic(wdf, ens, "paper")
+    assert traffic is not None, ("profiles/iv_paper_traffic.md was taken on other interaction kernels: "
+                                 "measure FETCH_SIZE / WRITE_SIZE again")
+    n, F = 3_000_000, 127
+    output = 4 * F * F * n
+    units = len(re.findall(r"const u32 q\d+ = ", wdf.iv_source(ens)))  # pattern reads per row
+    groups = ens.n_trees * 32  # pair groups of complete depth-6 trees
+    assert output <= traffic <= 1.1 * (output + (units + groups) * n)

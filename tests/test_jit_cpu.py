@@ -133,10 +133,10 @@ def test_iv_source_matches_the_layout(wdf, which):
     stores = [int(g) for g in re.findall(r"if \(row < ldp\) pb\[(\d+)\] = ", src)]
     assert len(stores) == len(set(stores)) == len(sets)
     assert all(s % 256 == 0 for s in stores)
-    # each case stores row i of the matrix: from o + i F ldo, one store per j,
-    # the address stepping by ldo
+    # each case stores row i of the matrix, non-temporally: from o + i F ldo,
+    # one store per j, the address stepping by ldo
     writes = []
-    for blk in src.split("gfp p = (gfp)(o + (i64)")[1:]:
+    for blk in src.split("gfp p = (gfp)o + (i64)")[1:]:
         base = int(blk[:blk.index(" ")])
         vals = re.findall(r"__builtin_nontemporal_store\((\S+), p\);", blk[:blk.index("} break;")])
         assert blk.count("p += ldo;") == len(vals) - 1
