@@ -42,12 +42,28 @@ struct JitPart {
   }
 };
 
+constexpr int kIvSideStreams = 3;  // streams besides the caller's that run interaction kernels
+
 struct JitModule {
   std::shared_ptr<JitPart> hist_part, explain_part;
   std::vector<std::shared_ptr<JitPart>> iv_parts;  // programs of the interaction and pattern kernels
   hipFunction_t hist = nullptr, explain = nullptr;
   std::vector<hipFunction_t> iv;  // interaction kernels, features [c * 4, c * 4 + 4)
   hipFunction_t patterns = nullptr;  // all groups' patterns of consumer rows, for the interaction kernels
+  // the interaction kernels of one chunk of rows run on the caller's stream
+  // and these (created with the kernels, default priority), forked from and
+  // joined back to the caller's stream by events; iv_mu orders the enqueues
+  // of calls from several host threads
+  hipStream_t iv_side[kIvSideStreams] = {};
+  hipEvent_t iv_fork = nullptr, iv_join[kIvSideStreams] = {};
+  std::mutex iv_mu;
+  ~JitModule() {
+    for (hipStream_t &x : iv_side)
+      if (x) (void)hipStreamDestroy(x);
+    if (iv_fork) (void)hipEventDestroy(iv_fork);
+    for (hipEvent_t &x : iv_join)
+      if (x) (void)hipEventDestroy(x);
+  }
 };
 
 namespace {
@@ -1073,6 +1089,7 @@ constexpr int kIvGatherBatch = 4;     // units whose table reads are issued toge
 constexpr int kIvPerKernel = 4;       // features per interaction kernel (compile time grows
                                       // faster than linearly with a function's size)
 constexpr int kIvKernelsPerProgram = 4;  // kernels per hipRTC program (programs compile in parallel)
+constexpr int64_t kIvChunkRows = 32768;  // consumer rows whose patterns all features' kernels read in turn
 
 // Resident blocks per CU and the LDS each takes, by the largest number of
 // partner accumulators among a kernel's features: three blocks (twelve waves)
@@ -1167,6 +1184,10 @@ int iv_kernel_count(const wdf_model *M) { return (M->n_features + kIvPerKernel -
 // types and macros of the interaction kernels
 std::string gen_iv_preamble() {
   std::ostringstream o;
+  // the launch configuration, recorded in the source (profiles keyed by the
+  // source's hash then follow launch changes too)
+  o << "// interaction kernels: rows in chunks of " << kIvChunkRows << ", " << kIvRows << "-row blocks, kernels over "
+    << 1 + kIvSideStreams << " streams\n";
   o << kPreamble << kStagePiece << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
     << "typedef float vf2 __attribute__((ext_vector_type(2)));\n"
     << "typedef const __attribute__((address_space(3))) unsigned char* lu8;\n"
@@ -1465,9 +1486,16 @@ int jit_build_iv(wdf_model *M) {
     }
     if (!again) break;
   }
-  M->jit->iv_parts = parts;
-  M->jit->iv = fns;
-  M->jit->patterns = parts.back()->fn;
+  JitModule &J = *M->jit;
+  hipError_t e = hipEventCreateWithFlags(&J.iv_fork, hipEventDisableTiming);
+  for (int k = 0; k < kIvSideStreams && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&J.iv_side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&J.iv_join[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return hip_error(e, "interaction streams");
+  J.iv_parts = parts;
+  J.iv = fns;
+  J.patterns = parts.back()->fn;
   return WDF_OK;
 }
 
@@ -1478,29 +1506,49 @@ int jit_explain_iv(const wdf_bg *bg, const float *X, int64_t ldx, uint8_t *pat, 
     return set_error(WDF_E_INVALID_ARG, "specialised interaction kernel missing");
   if (n <= 0) return WDF_OK;
   if ((uintptr_t)pat % 16) return set_error(WDF_E_INVALID_ARG, "interaction workspace not 16-byte aligned");
-  int64_t ldp = iv_pattern_stride(n);
-  {
-    const JitPlan &P = M->jp;
-    const float *thr = P.d_thr_pad.as<float>();
-    int live = 1;
-    void *pargs[] = {(void *)&X, &ldx, (void *)&thr, &pat, &n, &ldp, &live};
-    const size_t lds = (int64_t)P.thr_pad.size() <= kPatLdsThresholds ? P.thr_pad.size() * sizeof(float) : 0;
-    hipError_t e = hipModuleLaunchKernel(M->jit->patterns, (unsigned)(ldp / 256), 1, 1, 256, 1, 1, (unsigned)lds, s,
-                                         pargs, nullptr);
-    if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(patterns)");
-  }
+  JitModule &J = *M->jit;
+  std::lock_guard<std::mutex> lock(J.iv_mu);
+  const JitPlan &P = M->jp;
+  const float *thr = P.d_thr_pad.as<float>();
   const float *t2 = bg->d_xtab.as<float>();
-  int live = 1;
-  void *args[] = {(void *)&pat, &n, (void *)&t2, &iv, &ldiv, &live};
-  const unsigned blocks = (unsigned)((n + kIvRows - 1) / kIvRows);
+  const size_t lds = (int64_t)P.thr_pad.size() <= kPatLdsThresholds ? P.thr_pad.size() * sizeof(float) : 0;
+  const int64_t G = (int64_t)M->groups.size();
   const int F = M->n_features;
-  for (int c = 0; c < (int)M->jit->iv.size(); ++c) {
-    const unsigned fc = (unsigned)std::min(kIvPerKernel, F - c * kIvPerKernel);
-    hipError_t e =
-        hipModuleLaunchKernel(M->jit->iv[(size_t)c], blocks, fc, 1, kIvRows, 1, 1, 0, s, args, nullptr);
-    if (e != hipSuccess) return hip_error(e, "hipModuleLaunchKernel(interaction)");
+  // Rows in chunks of kIvChunkRows: the patterns of one chunk (G bytes per
+  // row) are written, then read by every feature's kernel while they are
+  // still in the device's last-level cache; the chunk's kernels are spread
+  // over the caller's stream and the side streams so that together they fill
+  // the device.  The next chunk's patterns (on the caller's stream) go to
+  // another part of the workspace, so they may overlap the side streams'
+  // kernels of this chunk.
+  int rc = WDF_OK;
+  for (int64_t r0 = 0; r0 < n && rc == WDF_OK; r0 += kIvChunkRows) {
+    int64_t m = std::min<int64_t>(kIvChunkRows, n - r0), ldp = iv_pattern_stride(m);
+    const float *Xc = X + r0;
+    uint8_t *pc = pat + r0 * G;
+    float *ivc = iv + r0;
+    int live = 1;
+    void *pargs[] = {(void *)&Xc, &ldx, (void *)&thr, &pc, &m, &ldp, &live};
+    hipError_t e = hipModuleLaunchKernel(J.patterns, (unsigned)(ldp / 256), 1, 1, 256, 1, 1, (unsigned)lds, s, pargs,
+                                         nullptr);
+    if (e == hipSuccess) e = hipEventRecord(J.iv_fork, s);
+    for (int k = 0; k < kIvSideStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(J.iv_side[k], J.iv_fork, 0);
+    void *args[] = {(void *)&pc, &m, (void *)&t2, &ivc, &ldiv, &live};
+    const unsigned blocks = (unsigned)((m + kIvRows - 1) / kIvRows);
+    for (int c = 0; c < (int)J.iv.size() && e == hipSuccess; ++c) {
+      const unsigned fc = (unsigned)std::min(kIvPerKernel, F - c * kIvPerKernel);
+      hipStream_t sc = c % (kIvSideStreams + 1) == 0 ? s : J.iv_side[c % (kIvSideStreams + 1) - 1];
+      e = hipModuleLaunchKernel(J.iv[(size_t)c], blocks, fc, 1, kIvRows, 1, 1, 0, sc, args, nullptr);
+    }
+    if (e != hipSuccess) rc = hip_error(e, "interaction launches");
   }
-  return WDF_OK;
+  // the caller's stream waits for the side streams' work (also after an error)
+  for (int k = 0; k < kIvSideStreams; ++k) {
+    hipError_t e = hipEventRecord(J.iv_join[k], J.iv_side[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, J.iv_join[k], 0);
+    if (e != hipSuccess && rc == WDF_OK) rc = hip_error(e, "interaction stream join");
+  }
+  return rc;
 }
 
 HistLaunch hist_launch(const wdf_model *M, int64_t m) {
