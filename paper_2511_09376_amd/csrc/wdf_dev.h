@@ -37,9 +37,10 @@ struct Group {
 // raw index r is r ^ mask.  Layout: E = 2^(depth + quad) entries of nv values,
 // stored as ceil(nv / 4) float4 planes [plane][slot], value v in component
 // v % 4 of plane v / 4 (unused components 0), so that one 16-byte LDS read
-// returns four values of an entry; entry I sits at slot I ^ (I >> 3) ^ (I >> 6)
-// of each plane, so that entries sharing their low three bits (one group of
-// LDS banks) are spread over all eight groups.
+// returns four values of an entry; entry I sits at slot
+// I ^ (I >> fold_a) ^ (I >> fold_b) of each plane (a bijection), the shifts
+// chosen per unit so that the entries rows are likely to read together fall
+// in different groups of LDS banks.
 struct XUnit {
   int64_t src_l;   // table offset of the (left) group
   int64_t src_r;   // table offset of the right pair group of a quad, -1 otherwise
@@ -48,7 +49,14 @@ struct XUnit {
   int32_t quad;    // 1 for a quad
   uint32_t mask;   // right turns: all d positions of a group, the d - 2 prefix positions of a quad
   int32_t nv;      // values per entry: depth + quad
+  int32_t fold_a;  // entry I sits at slot I ^ (I >> fold_a) ^ (I >> fold_b) of each plane (0: no term)
+  int32_t fold_b;
 };
+
+// slot of entry I in a plane of an explain-table unit
+constexpr int xunit_slot(const XUnit &u, int I) {
+  return I ^ (u.fold_a ? I >> u.fold_a : 0) ^ (u.fold_b ? I >> u.fold_b : 0);
+}
 
 // floats of a unit in the explain tables
 inline int64_t xunit_floats(const XUnit &u) {

@@ -72,6 +72,47 @@ namespace {
 // Plan: threshold ranks, histogram chunks, explain stages
 // ---------------------------------------------------------------------------
 
+// The fold of an explain-table unit (XUnit::fold_a, fold_b): slot shifts
+// that spread the entries rows tend to read together over the 16 groups of
+// LDS banks one 16-lane phase of a 16-byte read spans.  With the model's
+// covers, each index bit (a raw split, MSB first) is 1 with probability
+// cover(left child) / cover(node), the splits taken as independent; the fold
+// kept minimises the sum over bank groups of the squared probability mass in
+// the group (the chance that two reads hit one group, up to a term no fold
+// changes).  Shifts come from ancestors' patterns: at least 1 for a group, 2
+// for a quad (whose index has no register for I >> 1).  Without covers, or on
+// a tie: shifts 3 and 6 where below the index width.
+void choose_fold(const wdf_model *M, XUnit &u, int64_t tree, const std::vector<int64_t> &nodes) {
+  const int bits = u.depth + u.quad;
+  u.fold_a = bits > 3 ? 3 : 0;
+  u.fold_b = bits > 6 ? 6 : 0;
+  if (!M->has_cover || bits <= 4) return;  // up to 16 entries sit in distinct groups whatever the fold
+  const int E = 1 << bits;
+  const int64_t base = M->node_offset[(size_t)tree];
+  std::vector<double> P((size_t)E, 1.0);
+  for (int k = 0; k < bits; ++k) {
+    const int64_t nd = nodes[(size_t)k];
+    const double c = M->cover[(size_t)nd];
+    const double pl = c > 0 ? M->cover[(size_t)(base + M->left[(size_t)nd])] / c : 0.5;
+    for (int I = 0; I < E; ++I) P[(size_t)I] *= ((I >> (bits - 1 - k)) & 1) ? pl : 1.0 - pl;
+  }
+  auto cost = [&](int a, int b) {
+    double grp[16] = {};
+    for (int I = 0; I < E; ++I) grp[(I ^ (a ? I >> a : 0) ^ (b ? I >> b : 0)) & 15] += P[(size_t)I];
+    double c = 0.0;
+    for (double x : grp) c += x * x;
+    return c;
+  };
+  double best = cost(u.fold_a, u.fold_b);
+  const int lo = u.quad ? 2 : 1;
+  for (int a = lo; a < bits; ++a)
+    for (int b = 0; b < bits; ++b) {
+      if (b != 0 && b <= a) continue;
+      const double c = cost(a, b);
+      if (c < best * (1.0 - 1e-9)) best = c, u.fold_a = a, u.fold_b = b;
+    }
+}
+
 int make_plan(wdf_model *M) {
   JitPlan &P = M->jp;
   const int F = M->n_features;
@@ -232,6 +273,17 @@ int make_plan(wdf_model *M) {
     u.mask = 0;
     for (int k = 0; k < (quad ? ga.depth - 2 : ga.depth); ++k)
       u.mask = (u.mask << 1) | M->path[(size_t)ga.path_off + (size_t)k].dir;
+    {
+      // the nodes of the index bits: the group's path (and for a quad the
+      // right pair's node last)
+      std::vector<int64_t> nodes;
+      for (int k = 0; k < ga.depth; ++k) nodes.push_back(M->path_nodes[(size_t)ga.path_off + (size_t)k]);
+      if (quad) {
+        const Group &gb = M->groups[(size_t)g + 1];
+        nodes.push_back(M->path_nodes[(size_t)gb.path_off + (size_t)gb.depth - 1]);
+      }
+      choose_fold(M, u, ga.tree, nodes);
+    }
     xoff += xunit_floats(u);
     P.xunits.push_back(u);
     P.unit_g0.push_back(g);
@@ -354,13 +406,14 @@ struct Gen {
   };
 
   // Table slot of a unit's index `idx` of `bits` bits: the explain tables store
-  // entry I at I ^ (I >> 3) ^ (I >> 6) (a bijection), which spreads the entries
-  // that share their low three bits (one group of LDS banks for 16-byte rows)
-  // over all groups.  I >> 3 and I >> 6 are the patterns of two ancestors,
-  // already in registers, so the slot costs one three-input XOR.
-  std::string slot(const std::string &idx, int bits) {
+  // entry I at I ^ (I >> a) ^ (I >> b) (a bijection; the unit's fold, 0 for
+  // no term), which spreads entries over the groups of LDS banks.  I >> k is
+  // the pattern of an ancestor, already in a register, so the slot costs one
+  // three-input XOR.
+  std::string slot(const std::string &idx, int bits, int a, int b) {
     std::vector<std::string> t{idx};
-    for (int k = 3; k < bits; k += 3) t.push_back(chain[(size_t)(bits - k - 1)]);
+    for (int k : {a, b})
+      if (k) t.push_back(chain[(size_t)(bits - k - 1)]);
     if (t.size() == 1) return idx;
     const std::string v = "z" + idx;
     if (t.size() == 2) o << "const u32 " << v << " = " << t[0] << " ^ " << t[1] << ";\n";
@@ -790,7 +843,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     };
     auto gather = [&](const XUnit &x, const std::string &pidx, const std::vector<const PathNode *> &pos) {
       const int64_t E = (int64_t)1 << (x.depth + x.quad);
-      const std::string p = gen.slot(pidx, x.depth + x.quad);
+      const std::string p = gen.slot(pidx, x.depth + x.quad, x.fold_a, x.fold_b);
       static const char *C[4] = {"x", "y", "z", "w"};
       std::ostringstream adds;
       for (int j = 0; 4 * j < x.nv; ++j) {

@@ -659,9 +659,9 @@ __global__ __launch_bounds__(256) void k_xtab(const XUnit *__restrict__ units, c
   const float *tl = tab + u.src_l, *tr = tab + u.src_r;
   for (int i = threadIdx.x; i < planes * E * 4; i += blockDim.x) {
     const int v = (i / (4 * E)) * 4 + (i & 3), I = (i / 4) % E;
-    // entry I sits at slot I ^ (I >> 3) ^ (I >> 6) of its plane (a bijection
-    // on [0, E) that spreads entries over the LDS bank groups)
-    const int slot = (i / (4 * E)) * 4 * E + 4 * (I ^ (I >> 3) ^ (I >> 6)) + (i & 3);
+    // entry I sits at slot xunit_slot(I) of its plane (a bijection on [0, E)
+    // that spreads entries over the LDS bank groups)
+    const int slot = (i / (4 * E)) * 4 * E + 4 * xunit_slot(u, I) + (i & 3);
     float val = 0.f;
     if (v < u.nv) {
       if (!u.quad) {
