@@ -256,3 +256,23 @@ def test_feature_limits(wdf):
         with pytest.raises(wdf.WdfError) as e:
             wdf.specialised_source(_one_tree([F - 1, -1, -1], [1, -1, -1], [2, -1, -1], F))
         assert e.value.code == wdf.E_UNSUPPORTED and where in str(e.value), (F, str(e.value))
+
+
+def test_explain_folds_follow_the_covers(wdf):
+    """The explain tables' slot folds (entry I at I ^ (I >> a) ^ (I >> b)) are
+    chosen per unit from the model's covers: a model loaded without covers
+    gets the same gathers and adds with the default shifts, and with covers a
+    share of the units (not all: some keep the default, which is also chosen
+    on a tie) takes other shifts."""
+    import dataclasses
+    ens = synth.WORKLOADS["mid"].ensemble()
+    with_cover = _explain_body(wdf.specialised_source(ens))
+    without = _explain_body(wdf.specialised_source(dataclasses.replace(ens, cover=None)))
+    for a, b in ((with_cover, without),):
+        assert a.count("const vf4 g") == b.count("const vf4 g")
+        assert len(re.findall(r"f\d+ \+= g\d+\.", a)) == len(re.findall(r"f\d+ \+= g\d+\.", b))
+    slots = lambda src: re.findall(r"const u32 z\w+ = [^;]+;", src)
+    sw, sn = slots(with_cover), slots(without)
+    assert len(sw) > 0 and len(sn) > 0
+    differing = len(set(sw) - set(sn))
+    assert 0 < differing < len(sw)
