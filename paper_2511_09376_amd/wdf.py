@@ -100,10 +100,6 @@ def _close_all():
     _live.clear()
 
 
-def _finalizing() -> bool:
-    return sys.is_finalizing()
-
-
 class Tuning(C.Structure):
     _fields_ = [("quads", C.c_int), ("explain_rows", C.c_int), ("hist_rounds", C.c_int), ("hist_threads", C.c_int),
                 ("explain_ms", C.c_float * (MAX_DEPTH + 1)), ("explain_rows_ms", C.c_float * 2),
@@ -275,7 +271,9 @@ class Context:
             lib().wdf_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may already be cleared
+        # when the interpreter exits)
         if _finalizing():
             return
         try:
@@ -369,7 +367,9 @@ class Model:
             lib().wdf_model_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may already be cleared
+        # when the interpreter exits)
         if _finalizing():
             return
         try:
@@ -522,7 +522,9 @@ class Background:
             lib().wdf_bg_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may already be cleared
+        # when the interpreter exits)
         if _finalizing():
             return
         try:
@@ -565,7 +567,9 @@ class Graph:
             lib().wdf_graph_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may already be cleared
+        # when the interpreter exits)
         if _finalizing():
             return
         try:
@@ -624,7 +628,9 @@ class Server:
             lib().wdf_server_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: the module's globals may already be cleared
+        # when the interpreter exits)
         if _finalizing():
             return
         try:

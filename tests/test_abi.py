@@ -85,3 +85,25 @@ def test_missing_library_fails_loudly():
             "print('refused')\n")
     res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert res.returncode == 0 and res.stdout.strip() == "refused", res.stderr
+
+
+def test_handles_left_open_at_exit_close_quietly():
+    """Handles still referenced when the interpreter exits on an uncaught
+    error (torch imported, so the module teardown order is torch's) are
+    destroyed without an error from their finalizers."""
+    import subprocess
+    import sys
+    code = ("import torch\n"
+            "from paper_2511_09376_amd import wdf\n"
+            "objs = []\n"
+            "for cls in (wdf.Context, wdf.Model, wdf.Background, wdf.Graph, wdf.Server):\n"
+            "    o = cls.__new__(cls)\n"
+            "    o.h = None\n"
+            "    objs.append(o)\n"
+            "a, b, c, d, e = objs\n"
+            "def fail():\n"
+            "    raise ValueError('planned')\n"
+            "fail()\n")
+    res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 1 and "ValueError: planned" in res.stderr
+    assert "Exception ignored" not in res.stderr, res.stderr
