@@ -380,7 +380,9 @@ int wdf::validate_and_layout(const wdf_model_desc *d, wdf_model *M) {
     ClassInfo &c = M->cls[dp];
     c.h_off = ho;
     c.s_off = so;
-    ho += (int64_t)c.ncols << dp;
+    // classes start on 128-byte lines: the contraction reads column rows of
+    // 2^d' doubles with 16-byte loads
+    ho = (ho + ((int64_t)c.ncols << dp) + 15) & ~(int64_t)15;
     so += (int64_t)c.ncols * dp << dp;
   }
   M->h_total = ho;
@@ -661,10 +663,13 @@ static int alloc_tables(wdf_model *M, wdf_bg *bg, hipStream_t s) {
 }
 
 // The MFMA products S = M_{d'} H_{d'} of every distinct-feature class d'
-// (Section 7 steps (e)-(f)): one FP64 GEMM launch per class present.  *flops
+// (Section 7 steps (e)-(f)), all classes in one FP64 GEMM launch.  *flops
 // (when given) receives their floating-point operations, 2 R K per column.
+static_assert(kGemmMaxClasses >= WDF_MAX_DEPTH, "one launch holds every class d' = 1..WDF_MAX_DEPTH");
 static int enqueue_gemms(wdf_model *M, const wdf_bg *bg, const double *H, double *S, hipStream_t s, double *flops) {
   double f = 0.0;
+  GemmBatch batch{};
+  int waves = 0;
   for (int dp = bg->iv ? 2 : 1; dp <= WDF_MAX_DEPTH; ++dp) {
     const ClassInfo &c = M->cls[dp];
     if (c.ncols == 0) continue;
@@ -672,9 +677,11 @@ static int enqueue_gemms(wdf_model *M, const wdf_bg *bg, const double *H, double
     const double *coef = bg->iv ? M->d_coef_iv[bg->values - WDF_SHAPLEY_IV][dp].as<double>()
                                 : M->d_coef[bg->values][dp].as<double>();
     double *Sc = S + (bg->iv ? M->s_iv_class_off[dp] : c.s_off);
-    HIP_TRY(launch_gemm_f64(coef, H + c.h_off, Sc, R, K, c.ncols, s));
+    batch.c[batch.n++] = GemmClass{coef, H + c.h_off, Sc, R, K, c.ncols, waves};
+    waves += gemm_waves(R, c.ncols);
     f += 2.0 * (double)R * (double)K * (double)c.ncols;
   }
+  HIP_TRY(launch_gemm_f64(batch, waves, s));
   if (flops) *flops = f;
   return WDF_OK;
 }

@@ -17,7 +17,23 @@ hipError_t launch_patterns(const Group *groups, const PathNode *path, int64_t n_
 hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_groups, const uint32_t *hist,
                           const double *freq, const double *freq_r, double scale, const int64_t *class_off, double *H,
                           hipStream_t s);
-hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s);
+// The FP64 products of up to kGemmMaxClasses distinct-feature classes in one
+// launch: class i owns waves [c[i].wave0, c[i].wave0 + its 32x32 blocks).
+// K is a power of two; for K >= 16, M and H rows must be 16-byte aligned.
+constexpr int kGemmMaxClasses = 8;
+struct GemmClass {
+  const double *M;  // R x K, row-major
+  const double *H;  // ncols x K
+  double *S;        // ncols x R
+  int R, K, ncols, wave0;
+};
+struct GemmBatch {
+  GemmClass c[kGemmMaxClasses];
+  int n;
+};
+// 32x32 output blocks (waves) of one class
+inline int gemm_waves(int R, int ncols) { return ((R + 31) / 32) * ((ncols + 31) / 32); }
+hipError_t launch_gemm_f64(const GemmBatch &batch, int waves, hipStream_t s);
 hipError_t launch_expand(const Group *groups, const PathNode *path, int64_t n_groups, const int64_t *s_class_off,
                          const double *S, float *tab, double *tab64, hipStream_t s);
 hipError_t launch_base(const Group *groups, int64_t n_groups, const uint32_t *hist, const double *freq,

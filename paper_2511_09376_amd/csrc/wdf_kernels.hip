@@ -162,38 +162,23 @@ __global__ __launch_bounds__(256) void k_columns(const Group *__restrict__ group
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// S[col][r] = sum_k M[r][k] * H[col][k]  (M: R x K row-major, H: ncols x K).
-// One wave per 32x32 block of the output: 2 x 2 tiles of 16x16, each on
-// v_mfma_f64_16x16x4f64 over K; per step of 4 in K the wave loads two A and
-// two B fragments and issues four MFMAs (each fragment feeds two tiles).
-__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ M, const double *__restrict__ H,
-                                                  double *__restrict__ S, int R, int K, int ncols) {
-  const int lane = threadIdx.x & 63;
-  const int wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int blocks_r = (R + 31) >> 5, blocks_c = (ncols + 31) >> 5;
-  if (wave >= blocks_r * blocks_c) return;  // uniform per wave
-  const int br = wave % blocks_r, bc = wave / blocks_r;
-  const int i = lane & 15, kq = lane >> 4;
-  const int arow[2] = {br * 32 + i, br * 32 + 16 + i};
-  const int bcol[2] = {bc * 32 + i, bc * 32 + 16 + i};
-  v4d acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int kk = k0 + kq;
-    double a[2], b[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      a[h] = (arow[h] < R && kk < K) ? M[(int64_t)arow[h] * K + kk] : 0.0;
-      b[h] = (bcol[h] < ncols && kk < K) ? H[(int64_t)bcol[h] * K + kk] : 0.0;
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
-  }
+// S[col][r] = sum_k M[r][k] * H[col][k]  (M: R x K row-major, H: ncols x K)
+// for every distinct-feature class of the batch, in one launch.  One wave per
+// 32x32 block of a class's output: 2 x 2 tiles of 16x16, each on
+// v_mfma_f64_16x16x4f64 over K, so that each A and B fragment feeds two
+// MFMAs.  The waves of a class are consecutive (c[i].wave0 on), the row blocks
+// of one column block adjacent, so the four waves of a block share their B
+// lines in the CU's cache.
+//
+// K >= 16 (a power of two, operand rows 128-byte aligned): the sum over K is
+// taken in blocks of 16, where lane group q (lanes 16q..16q+15) supplies
+// k = k0 + 4q + s to the MFMA of step s = 0..3 (the same permutation of k for
+// A and B).  A lane's four values are then contiguous: two 16-byte loads per
+// operand and tile, and the four lane groups of a row read one whole 128-byte
+// line.  Rows or columns past the class's edge read row 0 instead; they only
+// reach outputs that are not stored.  Smaller K (d' <= 3) keeps the plain
+// order k = k0 + q with zeros past K.
+__device__ __forceinline__ void gemm_store(const GemmClass &c, int br, int bc, int lane, const v4d (&acc)[2][2]) {
   // in tile (x, y), output element (row 4*t + lane/16, column lane%16) sits in acc[x][y][t]
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -204,9 +189,111 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ M, 
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int rr = rbase + 4 * t;
-        if (rr < R && ccol < ncols) S[(int64_t)ccol * R + rr] = acc[x][y][t];
+        if (rr < c.R && ccol < c.ncols) c.S[(int64_t)ccol * c.R + rr] = acc[x][y][t];
       }
     }
+}
+
+__device__ __forceinline__ void gemm_wave_small(const GemmClass &c, int br, int bc, int lane) {
+  const int i = lane & 15, kq = lane >> 4;
+  const int arow[2] = {br * 32 + i, br * 32 + 16 + i};
+  const int bcol[2] = {bc * 32 + i, bc * 32 + 16 + i};
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < c.K; k0 += 4) {
+    const int kk = k0 + kq;
+    double a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = (arow[h] < c.R && kk < c.K) ? c.M[(int64_t)arow[h] * c.K + kk] : 0.0;
+      b[h] = (bcol[h] < c.ncols && kk < c.K) ? c.H[(int64_t)bcol[h] * c.K + kk] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+  }
+  gemm_store(c, br, bc, lane, acc);
+}
+
+// fragments of one block of 16 k values: [tile][pair of k]
+struct GemmFrag {
+  double2 a[2][2], b[2][2];
+};
+
+__device__ __forceinline__ void gemm_load(GemmFrag &f, const double2 *const (&pa)[2], const double2 *const (&pb)[2],
+                                          int k2) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    f.a[h][0] = pa[h][k2];
+    f.a[h][1] = pa[h][k2 + 1];
+    f.b[h][0] = pb[h][k2];
+    f.b[h][1] = pb[h][k2 + 1];
+  }
+}
+
+__device__ __forceinline__ void gemm_mfma16(const GemmFrag &f, v4d (&acc)[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const double av = (s & 1) ? f.a[x][s >> 1].y : f.a[x][s >> 1].x;
+        const double bv = (s & 1) ? f.b[y][s >> 1].y : f.b[y][s >> 1].x;
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[x][y], 0, 0, 0);
+      }
+}
+
+__device__ __forceinline__ void gemm_wave_wide(const GemmClass &c, int br, int bc, int lane) {
+  const int i = lane & 15, kq = lane >> 4;
+  const double2 *pa[2], *pb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = br * 32 + 16 * h + i, col = bc * 32 + 16 * h + i;
+    pa[h] = (const double2 *)(c.M + (int64_t)(r < c.R ? r : 0) * c.K + 4 * kq);
+    pb[h] = (const double2 *)(c.H + (int64_t)(col < c.ncols ? col : 0) * c.K + 4 * kq);
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+  // two fragment buffers: one block's loads are in flight while the other's
+  // MFMAs run (indices in double2 units: a block of 16 k is 8 of them).  The
+  // loads are unconditional, so that the waits count only the older buffer's;
+  // past the end of K they re-read the current block, and those values are
+  // not used.
+  GemmFrag f0, f1;
+  const int K2 = c.K / 2;
+  gemm_load(f0, pa, pb, 0);
+  for (int k2 = 0; k2 < K2; k2 += 16) {
+    const bool second = k2 + 8 < K2;
+    gemm_load(f1, pa, pb, second ? k2 + 8 : k2);
+    gemm_mfma16(f0, acc);
+    gemm_load(f0, pa, pb, k2 + 16 < K2 ? k2 + 16 : k2);
+    if (second) gemm_mfma16(f1, acc);
+  }
+  gemm_store(c, br, bc, lane, acc);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmBatch batch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // this wave's class (constant indices only: the batch stays in kernel arguments)
+  GemmClass c = batch.c[0];
+#pragma unroll
+  for (int k = 1; k < kGemmMaxClasses; ++k)
+    if (k < batch.n && wave >= batch.c[k].wave0) c = batch.c[k];
+  const int w = wave - c.wave0;
+  const int blocks_r = (c.R + 31) >> 5, blocks_c = (c.ncols + 31) >> 5;
+  if (w >= blocks_r * blocks_c) return;  // uniform per wave
+  const int br = w % blocks_r, bc = w / blocks_r;
+  if (c.K >= 16) gemm_wave_wide(c, br, bc, lane);
+  else gemm_wave_small(c, br, bc, lane);
 }
 
 // tab[g][k][p] = S_l[merge(k)][g(p)] + S_r[merge(k)][g(p ^ 1)] at the first
@@ -327,10 +414,9 @@ hipError_t launch_columns(const Group *groups, const PathNode *path, int64_t n_g
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_f64(const double *M, const double *H, double *S, int R, int K, int ncols, hipStream_t s) {
-  if (ncols <= 0 || R <= 0) return hipSuccess;
-  const int waves = ((R + 31) / 32) * ((ncols + 31) / 32);
-  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, M, H, S, R, K, ncols);
+hipError_t launch_gemm_f64(const GemmBatch &batch, int waves, hipStream_t s) {
+  if (waves <= 0 || batch.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, batch);
   return hipGetLastError();
 }
 
