@@ -463,11 +463,9 @@ constexpr int kQuantLds = 4096;
 // the rows of one block; T is the word's thresholds (LDS or global memory),
 // off[k] the block of its k-th feature inside T
 __device__ __forceinline__ void quantize_rows(const float *__restrict__ T, const int (&off)[4], const int (&c)[4],
-                                              int cmax, const float *__restrict__ X, int64_t n, int64_t ldx, int f0,
-                                              int nf, int bits, uint32_t *__restrict__ out) {
+                                              int cmax, const float *__restrict__ X, int64_t r0, int64_t r1,
+                                              int64_t ldx, int f0, int nf, int bits, uint32_t *__restrict__ out) {
   const uint32_t nan_code = 1u << (bits - 1);
-  const int64_t r0 = (int64_t)blockIdx.x * kQuantRows;
-  const int64_t r1 = r0 + kQuantRows < n ? r0 + kQuantRows : n;
   // two rows per thread and iteration (r and r + 256; the second re-reads the
   // first when past the end and is not stored), so that their loads and
   // searches overlap
@@ -506,9 +504,55 @@ __device__ __forceinline__ void quantize_rows(const float *__restrict__ T, const
   }
 }
 
+// The same for four consecutive rows per thread: X and the codes are read and
+// written with 16-byte accesses (row offsets, ldx and ldc multiples of four,
+// 16-byte aligned bases), and a thread runs sixteen searches side by side.
+// The last one to three rows of the matrix go through the row-wise loop.
+__device__ __forceinline__ void quantize_rows4(const float *__restrict__ T, const int (&off)[4], const int (&c)[4],
+                                               int cmax, const float *__restrict__ X, int64_t r0, int64_t r1,
+                                               int64_t ldx, int f0, int nf, int bits, uint32_t *__restrict__ out) {
+  const uint32_t nan_code = 1u << (bits - 1);
+  const int64_t rw = r0 + ((r1 - r0) & ~(int64_t)3);  // end of the whole groups of four
+  for (int64_t r = r0 + 4 * (int64_t)threadIdx.x; r < rw; r += 4 * 256) {
+    float x[4][4];  // [feature][row]
+    int p[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // features past the word's last re-read its first; their ranks are not used
+      const float4 v = *(const float4 *)(X + (int64_t)(f0 + (k < nf ? k : 0)) * ldx + r);
+      x[k][0] = v.x;
+      x[k][1] = v.y;
+      x[k][2] = v.z;
+      x[k][3] = v.w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p[k][j] = 0;
+    }
+    for (int sidx = cmax - 1; sidx >= 0; --sidx) {
+      const int step = 1 << sidx;
+      float t[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[k][j] = T[sidx < c[k] ? off[k] + p[k][j] + step - 1 : off[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[k][j] += (sidx < c[k] && t[k][j] <= x[k][j]) ? step : 0;
+    }
+    uint32_t word[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k < nf) word[j] |= (x[k][j] != x[k][j] ? nan_code : (uint32_t)p[k][j]) << (k * bits);
+    *(uint4 *)(out + r) = make_uint4(word[0], word[1], word[2], word[3]);
+  }
+  if (rw < r1) quantize_rows(T, off, c, cmax, X, rw, r1, ldx, f0, nf, bits, out);
+}
+
 __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t n, int64_t ldx, int F,
                                                   const float *__restrict__ thr_pad, const int2 *__restrict__ meta,
-                                                  int wide, uint32_t *__restrict__ codes, int64_t ldc) {
+                                                  int wide, uint32_t *__restrict__ codes, int64_t ldc, int vec4) {
   __shared__ float st[kQuantLds];
   const int w = blockIdx.y;
   const int per = wide ? 2 : 4, bits = wide ? 16 : 8;
@@ -530,20 +574,25 @@ __global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, i
 #pragma unroll
   for (int k = 0; k < 4; ++k) off[k] = c[k] > 0 ? off[k] - lo : 0;
   uint32_t *out = codes + (int64_t)w * ldc;
+  const int64_t r0 = (int64_t)blockIdx.x * kQuantRows;
+  const int64_t r1 = r0 + kQuantRows < n ? r0 + kQuantRows : n;
   if (hi - lo <= kQuantLds) {
     for (int i = threadIdx.x; i < hi - lo; i += 256) st[i] = thr_pad[lo + i];
     __syncthreads();
-    quantize_rows(st, off, c, cmax, X, n, ldx, f0, nf, bits, out);
+    if (vec4) quantize_rows4(st, off, c, cmax, X, r0, r1, ldx, f0, nf, bits, out);
+    else quantize_rows(st, off, c, cmax, X, r0, r1, ldx, f0, nf, bits, out);
   } else {
-    quantize_rows(thr_pad + lo, off, c, cmax, X, n, ldx, f0, nf, bits, out);
+    if (vec4) quantize_rows4(thr_pad + lo, off, c, cmax, X, r0, r1, ldx, f0, nf, bits, out);
+    else quantize_rows(thr_pad + lo, off, c, cmax, X, r0, r1, ldx, f0, nf, bits, out);
   }
 }
 
 hipError_t launch_quantize(const float *X, int64_t n, int64_t ldx, int F, const float *thr_pad, const int2 *meta,
                            int wide, int words, uint32_t *codes, int64_t ldc, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  const int vec4 = ldx % 4 == 0 && ldc % 4 == 0 && ((uintptr_t)X & 15u) == 0 && ((uintptr_t)codes & 15u) == 0;
   hipLaunchKernelGGL(k_quantize, dim3((unsigned)((n + kQuantRows - 1) / kQuantRows), (unsigned)words), dim3(256), 0, s,
-                     X, n, ldx, F, thr_pad, meta, wide, codes, ldc);
+                     X, n, ldx, F, thr_pad, meta, wide, codes, ldc, vec4);
   return hipGetLastError();
 }
 

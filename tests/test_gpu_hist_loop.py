@@ -69,3 +69,20 @@ def test_mid_tile_loop_bit_exact(wdf, mid, threads, rounds):
     assert_histograms_equal(groups, bg.histograms(), ens, B2, cache=cache)
     g.close()
     bg.close()
+
+
+def test_mid_tile_loop_whole_groups_of_four(wdf, mid):
+    """300 004 background rows: a multiple of four, so the quantize kernel
+    reads the rows and writes their codes 16 bytes at a time before the same
+    tile loop counts them (4688 tiles, the last one holding 36 rows)."""
+    ens, ctx, model, B, B2, cache = mid
+    m = M_ROWS - 3
+    model.set_tuning({"hist_threads": 1024, "hist_rounds": 2})
+    L = model.hist_launch(m)
+    print(f"[hist loop] {m} rows: {L['blocks']} blocks x {L['chunks']} chunks, "
+          f"up to {L['tiles_per_wave']} tiles per wave", flush=True)
+    assert m % 4 == 0 and L["tiles"] * 64 > m and L["tiles_per_wave"] >= 4
+    Bs = np.ascontiguousarray(B[:, :m])
+    bg = wdf.Background(model, torch.from_numpy(Bs).cuda())
+    assert assert_histograms_equal(model.groups(), bg.histograms(), ens, Bs) == model.groups()["depth"].size
+    bg.close()

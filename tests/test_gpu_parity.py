@@ -126,10 +126,14 @@ def mid():
     return w, w.ensemble(), w.consumers(), w.background()
 
 
+@pytest.mark.parametrize("m", [20011, 20012])
 @pytest.mark.parametrize("kname", KERNELS)
-def test_mid_histograms_bit_exact(wdf, ctx, mid, kname):
+def test_mid_histograms_bit_exact(wdf, ctx, mid, kname, m):
+    """Several tiles and a ragged tail; a row count divisible by four (and so
+    a code stride of whole 16-byte groups) takes the quantize kernel's
+    four-rows-per-thread path, the other its row-wise path."""
     w, ens, X, B = mid
-    Bs = np.ascontiguousarray(B[:, :20011])   # several tiles and a ragged tail
+    Bs = np.ascontiguousarray(B[:, :m])
     om = oracle.Model(ens)
     model = _load(wdf, ctx, ens, kname)
     groups = model.groups()
