@@ -777,7 +777,10 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n"
     << "#define EXPLAIN_NAME " << explain_kernel_name(P) << "\n"
     << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
-    << "typedef const __attribute__((address_space(3))) vf4* lvf4;  // an LDS address (32 bits)\n";
+    << "typedef const __attribute__((address_space(3))) vf4* lvf4;  // an LDS address (32 bits)\n"
+    << "// a table component that adds to no feature (a zero): used by an empty asm,\n"
+    << "// so that the read stays 16 bytes wide without an instruction for it\n"
+    << "#define KEEP(v) asm volatile(\"\" :: \"v\"(v))\n";
   o << kStagePiece << R"(// one row per lane, one tile of NT rows per block
 extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __restrict__ X, i64 ldx,
                                                                      const float* __restrict__ tab,
@@ -812,7 +815,6 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   emit_rank_words(o, M, used, P.thr_in_lds);
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
-  o << "  float sink = 0.f;  // unused table components (zeros)\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
   if (!thr_hi) emit_stage_copy(o, t0, 0, n16, P.nt_explain);
   o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
@@ -828,8 +830,9 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     // One 16-byte read per float4 plane returns four values of the entry;
     // value v adds to the feature of its path position when that position is
     // the feature's first on the path.  Components that add to no feature
-    // (zeros in the tables) add to `sink`, so that no read is narrowed to an
-    // 8- or 12-byte one (more LDS cycles per value on random addresses).  The
+    // (zeros in the tables) are kept by an empty asm (KEEP), so that no read is
+    // narrowed to an 8- or 12-byte one (more LDS cycles per value on random
+    // addresses) and no instruction is spent on them.  The
     // reads of kGatherBatch units are issued before their adds, with a
     // scheduling barrier between, so that that many are in flight (the
     // compiler otherwise reads, waits and adds one unit at a time).
@@ -867,7 +870,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
         for (int c = 0; c < 4; ++c) {
           const bool real = 4 * j + c < x.nv && pos[(size_t)(4 * j + c)]->first;
           if (real) adds << " f" << pos[(size_t)(4 * j + c)]->feat << " += " << gv << "." << C[c] << ";";
-          else adds << " sink += " << gv << "." << C[c] << ";";
+          else adds << " KEEP(" << gv << "." << C[c] << ");";
         }
       }
       pending += adds.str() + "\n";
@@ -915,7 +918,6 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     o.str("");
     o << body;
   }
-  o << "  if (live == 2) phi[row] = sink;  // never (live is 1): keeps the sink's reads whole\n";
   o << "  if (row < n) {\n";
   for (int f = 0; f < F; ++f) o << "    phi[" << f << " * ldphi + row] = " << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ";\n";
   o << "  }\n}\n";
