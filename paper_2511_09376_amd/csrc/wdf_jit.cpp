@@ -754,6 +754,17 @@ const char *kStagePiece = R"(
                                    (__attribute__((address_space(3))) void*)((dst) + 4 * (c) + wbase4), 16, 0, 0)
 )";
 
+// The explain kernel's stage copies: buffer loads straight into LDS through
+// a descriptor of the explain tables (base, size in bytes), the lane's byte
+// offset in one VGPR and each piece's uniform offset in an SGPR, so that a
+// copy instruction needs no vector address arithmetic.  Reads past the
+// descriptor's size return zeros instead of faulting.
+const char *kStagePieceBuf = R"(
+#define STAGE_PIECE_B(sofs, dst, c) \
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(trs, (__attribute__((address_space(3))) void*)((dst) + 4 * (c) + wbase4), \
+                                           16, tvoff, (sofs) + 16 * (c), 0, 0)
+)";
+
 constexpr int kGatherBatch = 4;  // explain units whose table reads are in flight together
 
 // Unrolled copy of n16 16-byte pieces from tab + t0 to LDS at dst_off floats:
@@ -763,6 +774,16 @@ void emit_stage_copy(std::ostream &o, int64_t t0, int64_t dst_off, int64_t n16, 
   int64_t c = 0;
   for (; c + nt <= n16; c += nt) o << " STAGE_PIECE(s_, d_, " << c << ");";
   if (c < n16) o << " if (threadIdx.x < " << (n16 - c) << "u) STAGE_PIECE(s_, d_, " << c << ");";
+  o << " }\n";
+}
+
+// The same copy for the explain kernel, through its table descriptor (byte
+// offsets from the start of the explain tables).
+void emit_stage_copy_buf(std::ostream &o, int64_t t0, int64_t dst_off, int64_t n16, int nt) {
+  o << "  { float* d_ = lds + " << dst_off << ";";
+  int64_t c = 0;
+  for (; c + nt <= n16; c += nt) o << " STAGE_PIECE_B(" << 4 * t0 << "u, d_, " << c << "u);";
+  if (c < n16) o << " if (threadIdx.x < " << (n16 - c) << "u) STAGE_PIECE_B(" << 4 * t0 << "u, d_, " << c << "u);";
   o << " }\n";
 }
 
@@ -776,12 +797,17 @@ std::string gen_explain(const wdf_model *M, const TreeIndex &ix) {
   o << kPreamble;
   o << "#define NT " << P.nt_explain << "\n#define SF " << P.stage_floats << "\n#define TF " << P.thr_pad.size() << "\n"
     << "#define EXPLAIN_NAME " << explain_kernel_name(P) << "\n"
+    << "#define TAB_BYTES " << 4 * P.xtab_size << "  // bytes of the explain tables\n"
     << "typedef float vf4 __attribute__((ext_vector_type(4)));\n"
     << "typedef const __attribute__((address_space(3))) vf4* lvf4;  // an LDS address (32 bits)\n"
     << "// a table component that adds to no feature (a zero): used by an empty asm,\n"
     << "// so that the read stays 16 bytes wide without an instruction for it\n"
     << "#define KEEP(v) asm volatile(\"\" :: \"v\"(v))\n";
-  o << kStagePiece << R"(// one row per lane, one tile of NT rows per block
+  // stage copies through a buffer descriptor while the tables' byte offsets
+  // fit its 31-bit size (every realistic model), else global addresses
+  const bool buf_copy = 4 * P.xtab_size <= 0x7fffffffll;
+  auto copy = buf_copy ? emit_stage_copy_buf : emit_stage_copy;
+  o << (buf_copy ? kStagePieceBuf : kStagePiece) << R"(// one row per lane, one tile of NT rows per block
 extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __restrict__ X, i64 ldx,
                                                                      const float* __restrict__ tab,
                                                                      const float* __restrict__ thr,
@@ -792,6 +818,10 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   const i64 row = (i64)blockIdx.x * NT + threadIdx.x;
   const i64 rr = row < n ? row : n - 1;
 )";
+  if (buf_copy)
+    o << "  const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc((void*)tab, (short)0, TAB_BYTES, "
+         "0x00020000);\n"
+      << "  const u32 tvoff = threadIdx.x * 16u;  // the lane's piece of a chunk, in bytes\n";
   const auto &S = P.explain_stages;
   // unit of every group, and the explain-table span of a stage
   std::vector<int64_t> unit_of(M->groups.size());
@@ -808,7 +838,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   // thresholds in the second stage buffer when they fit there, so that the
   // first stage loads during the rank search; else across both buffers
   const bool thr_hi = P.thr_in_lds && (int64_t)P.thr_pad.size() <= P.stage_floats;
-  if (thr_hi) emit_stage_copy(o, t0, 0, n16, P.nt_explain);
+  if (thr_hi) copy(o, t0, 0, n16, P.nt_explain);
   if (P.thr_in_lds)
     o << "  float* lthr = lds + " << (thr_hi ? P.stage_floats : 0) << ";\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
@@ -816,7 +846,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
-  if (!thr_hi) emit_stage_copy(o, t0, 0, n16, P.nt_explain);
+  if (!thr_hi) copy(o, t0, 0, n16, P.nt_explain);
   o << "  __builtin_amdgcn_s_waitcnt(0);\n  __syncthreads();\n";
   o << "  LDS_BASES\n";
   std::set<int64_t> lds_bases;  // 32 KiB steps of the LDS the gathers address from a base register
@@ -824,7 +854,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     const int buf = (int)(s & 1);
     if (s + 1 < S.size()) {
       stage_span(s + 1, t0, n16);
-      emit_stage_copy(o, t0, (int64_t)(1 - buf) * P.stage_floats, n16, P.nt_explain);
+      copy(o, t0, (int64_t)(1 - buf) * P.stage_floats, n16, P.nt_explain);
     }
     const int64_t sbase = P.xunits[(size_t)unit_of[(size_t)S[s].first]].dst;
     // One 16-byte read per float4 plane returns four values of the entry;
