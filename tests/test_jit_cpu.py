@@ -108,6 +108,29 @@ def _path_feature_sets(ens):
     return out
 
 
+def test_explain_stage_copies_and_zero_components(wdf):
+    """The explain kernel copies its table stages with buffer loads into LDS
+    through a descriptor sized to the explain tables (offsets in scalar
+    registers), keeps zero table components with an empty asm (no sink add,
+    no sink store), and every copy piece lies inside the tables."""
+    ens = synth.WORKLOADS["mid"].ensemble()
+    body = _explain_body(wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED))
+    assert "__builtin_amdgcn_make_buffer_rsrc" in body and "STAGE_PIECE_B(" in body
+    assert "STAGE_PIECE(" not in body and "global_load_lds" not in body
+    assert "sink" not in body and "KEEP(" in body
+    tab_bytes = int(re.search(r"#define TAB_BYTES (\d+)", body).group(1))
+    nt = int(re.search(r"#define NT (\d+)", wdf.specialised_source(ens, kernel=wdf.KERNEL_SPECIALISED)).group(1))
+    # thread t of a chunk reads 16 bytes at byte (stage offset + 16 (c + t)); a
+    # chunk is unguarded (all NT threads) or guarded by the threads it covers
+    pieces = re.findall(r"(if \(threadIdx\.x < (\d+)u\) )?STAGE_PIECE_B\((\d+)u, d_, (\d+)u\)", body)
+    assert pieces
+    for guard, lim, ofs, c in pieces:
+        ofs, c = int(ofs), int(c)
+        threads = int(lim) if guard else nt
+        assert ofs % 16 == 0 and c % nt == 0 and 0 < threads <= nt
+        assert ofs + 16 * (c + threads) <= tab_bytes
+
+
 @pytest.mark.parametrize("which", ["small", "edge"])
 def test_iv_source_matches_the_layout(wdf, which):
     """The specialised interaction kernels add one pair value per (group,
