@@ -697,7 +697,10 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
 // the pattern code expects; thresholds from lthr (LDS) or thr.  The searches
 // run step-major over batches of 16 features so that 16 independent reads
 // are in flight at every step.
-void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char> &used, bool lds_thr) {
+// nt: the row's values are read with non-temporal loads (read once, kept out
+// of the way of data the caller's kernel reuses from the caches).
+void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char> &used, bool lds_thr,
+                     bool nt = false) {
   const JitPlan &P = M->jp;
   const int F = M->n_features;
   for (int w = 0; w < P.words; ++w) o << "  u32 w" << w << ";\n";
@@ -716,7 +719,11 @@ void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char
     int cmax = 0;
     for (size_t i = b0; i < b1; ++i) {
       const int f = uf[i];
-      o << "  const float x" << f << " = X[(i64)" << f << " * ldx + rr]; u32 r" << f << " = 0u;\n";
+      if (nt)
+        o << "  const float x" << f << " = __builtin_nontemporal_load(&X[(i64)" << f << " * ldx + rr]); u32 r" << f
+          << " = 0u;\n";
+      else
+        o << "  const float x" << f << " = X[(i64)" << f << " * ldx + rr]; u32 r" << f << " = 0u;\n";
       cmax = std::max(cmax, P.thr_steps[(size_t)f]);
     }
     for (int k = cmax - 1; k >= 0; --k) {
@@ -842,7 +849,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
   if (P.thr_in_lds)
     o << "  float* lthr = lds + " << (thr_hi ? P.stage_floats : 0) << ";\n"
       << "  for (int i = threadIdx.x; i < TF; i += NT) lthr[i] = thr[i];\n  __syncthreads();\n";
-  emit_rank_words(o, M, used, P.thr_in_lds);
+  emit_rank_words(o, M, used, P.thr_in_lds, true);
   for (int f = 0; f < F; ++f)
     if (used[(size_t)f]) o << "  float f" << f << " = 0.f;\n";
   if (P.thr_in_lds && !thr_hi) o << "  __syncthreads();\n";  // every wave is done with the thresholds
@@ -949,7 +956,11 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     o << body;
   }
   o << "  if (row < n) {\n";
-  for (int f = 0; f < F; ++f) o << "    phi[" << f << " * ldphi + row] = " << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ";\n";
+  // phi is written once and not read again here: non-temporal stores, so
+  // that it does not evict the table stages from the L2
+  for (int f = 0; f < F; ++f)
+    o << "    __builtin_nontemporal_store(" << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ", &phi[" << f
+      << " * ldphi + row]);\n";
   o << "  }\n}\n";
   return o.str();
 }
