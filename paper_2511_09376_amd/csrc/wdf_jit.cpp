@@ -697,8 +697,7 @@ std::string gen_hist(const wdf_model *M, const TreeIndex &ix) {
 // the pattern code expects; thresholds from lthr (LDS) or thr.  The searches
 // run step-major over batches of 16 features so that 16 independent reads
 // are in flight at every step.
-// nt: the row's values are read with non-temporal loads (read once, kept out
-// of the way of data the caller's kernel reuses from the caches).
+// nt: the row's values are read with non-temporal loads (each is read once).
 void emit_rank_words(std::ostream &o, const wdf_model *M, const std::vector<char> &used, bool lds_thr,
                      bool nt = false) {
   const JitPlan &P = M->jp;
@@ -956,8 +955,7 @@ extern "C" __global__ __launch_bounds__(NT, 2) void EXPLAIN_NAME(const float* __
     o << body;
   }
   o << "  if (row < n) {\n";
-  // phi is written once and not read again here: non-temporal stores, so
-  // that it does not evict the table stages from the L2
+  // phi is written once per launch and not read back: non-temporal stores
   for (int f = 0; f < F; ++f)
     o << "    __builtin_nontemporal_store(" << (used[(size_t)f] ? "f" + std::to_string(f) : "0.f") << ", &phi[" << f
       << " * ldphi + row]);\n";
