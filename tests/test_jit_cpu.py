@@ -108,6 +108,18 @@ def _path_feature_sets(ens):
     return out
 
 
+def test_multi_stage_kernels_compile(wdf):
+    """The 100-tree depth-6 model's generated kernels compile for gfx950 with
+    hipRTC: its explain kernel streams the tables through many stages (the
+    small models' kernels have one or two), so every per-stage code path of
+    the generator is compiled."""
+    ens = synth.WORKLOADS["mid"].ensemble()
+    src = wdf.specialised_source(ens, compile=True, kernel=wdf.KERNEL_SPECIALISED)
+    body = _explain_body(src)
+    assert body.count("__syncthreads();") >= 8
+    assert body.count("STAGE_PIECE_B(") > 8
+
+
 def test_explain_stage_copies_and_zero_components(wdf):
     """The explain kernel copies its table stages with buffer loads into LDS
     through a descriptor sized to the explain tables (offsets in scalar
